@@ -1,0 +1,44 @@
+"""FP64 CPU oracle for the spin-F BEC ground-state hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library, its
+Python binding) may import, call or link this package; only the tests, the
+smoke check and the CPU-baseline leg of the benchmark do.  It shares no code
+with the GPU path: it keeps its own spin tables, grid, Laplacian, energy,
+gradient, Hessian-vector product, manifold projection, retractions and
+solver, all written from the paper (Tian, Cai, Wu, Wen, "Ground states and
+their characterization of spin-F Bose-Einstein condensates") in complex128 /
+float64 with NumPy and scipy.fft.
+
+Each function cites the passage of the paper it follows.  Everything here is
+the plain definition: the matrix forms of Sec. 3 (with dense spin matrices),
+the projection and Hessian of Lemmas 4.1 and 4.2, the retractions of
+Lemmas 5.1, 5.3 and 5.5 and Algorithm 1.  No blocking, fusion or reordering
+beyond what those definitions state.
+
+Parity status of each part is listed in ``PINS``; a part without a pin to
+something other than itself says "parity unpinned".
+"""
+
+from .model import Problem, make_problem
+from .spin import spin_tables
+from .energy import laplacian, energy, grad, hvp, densities
+from .manifold import inner, proj_coeffs, project, rgrad, rhess, constraints
+from .retraction import retract_r1, retract_r2, retract_r3, retract
+from .solver import SolveOpts, solve, rgbb, arnt, tcg
+
+PINS = {
+    "laplacian": "naive DFT of the discrete Laplace formula; plane-wave eigenpairs",
+    "energy/grad": "harmonic closed form (E = sum(gamma)/2); finite differences",
+    "hvp": "finite differences; phase/spin-rotation/homogeneity identities; symmetry",
+    "projection/rgrad/rhess": "tangency, idempotence, Lemma 4.1 closed form",
+    "retractions": "constraints exact; R(0)=u; second order; R1 = brute-force nearest point; "
+                   "Lemma 5.2 cases 1-3",
+    "solver": "paper Table 3-1 / Table 4-1 printed ground-state energies (1D)",
+}
+
+__all__ = [
+    "Problem", "make_problem", "spin_tables", "laplacian", "energy", "grad", "hvp",
+    "densities", "inner", "proj_coeffs", "project", "rgrad", "rhess", "constraints",
+    "retract_r1", "retract_r2", "retract_r3", "retract", "SolveOpts", "solve", "rgbb",
+    "arnt", "tcg", "PINS",
+]

@@ -1,0 +1,227 @@
+"""Algorithm 1 on one mesh: RGBB warm start, then the modified ARNT (Sec. 5).
+
+RGBB (Sec. 5, eq. NMN and the text around it): steepest descent on the
+manifold with the Barzilai-Borwein step gamma_k = |<s,v>| / <v,v>, a
+nonmonotone Armijo test against C_k with the Zhang-Hager update
+C_{k+1} = (varrho Q_k C_k + E_{k+1}) / Q_{k+1}, Q_{k+1} = varrho Q_k + 1.
+
+ARNT (Sec. 5, eq. prob-sub .. eq. ratio, Algorithm 1): at u_k the model
+m_k(u) = <g, u-u_k> + 1/2 <H (u-u_k), u-u_k> + sigma_k/2 ||u-u_k||^2
+(g, H the Euclidean gradient and Hessian) is reduced by a truncated CG on
+grad m_k + Hess m_k[xi] = 0 that stops on accuracy or on negative curvature and
+returns s_k, d_k; the direction is xi_k = s_k + tau_k d_k (eq. xi); a monotone
+Armijo curvilinear search on m_k along R_{u_k}(alpha0 delta^j xi_k)
+(eq. tp1, tp2) gives the trial point z_k; the ratio rho_k of eq. ratio decides
+acceptance and the update of sigma (Algorithm 1); sigma_k = sigma_hat_k ||grad||
+with sigma_hat_0 = 1 and the sigma_est reset of Sec. 7.1.
+
+Parameters the paper leaves open are taken as follows (readings, listed in the
+design notes): the truncated CG itself is not printed (it is the one of the
+cited ARNT paper); it is plain CG from 0 with stopping rule
+||r|| <= min(T, ||g||^theta) ||g||, T = 0.1, theta = 1, and stops on curvature
+kappa = <p, A p> <= 1e-12 max(1, ||g||) ||p||^2, returning s = z (or -g at the
+first iteration), d = p when kappa < 0, sigma_est = |kappa| / ||p||^2.
+alpha0 = 1, rho = 1e-4, delta = 0.2, at most 30 backtracks.  sigma_hat is
+multiplied by gamma0 = 0.2 when rho_k >= eta2, by gamma1 = 1 when
+eta1 <= rho_k < eta2, by gamma2 = 10 on rejection.  RGBB: rho = 1e-4,
+delta = 0.2, varrho = 0.85, first step 0.1/||grad||, BB step clamped to
+[1e-20, 1e20].  Inner iterations capped at 500.  When both the energy change
+and the model value are below 16 eps |E| the ratio is taken as 1.  Twelve
+rejections in a row end the run unconverged (the tolerance lies below what
+FP64 energies resolve).
+"""
+
+from dataclasses import dataclass, field
+import numpy as np
+
+from .energy import energy, grad as egrad, hvp as ehvp, laplacian
+from .manifold import inner, rgrad, rhess
+from .retraction import retract, psi
+
+
+@dataclass
+class SolveOpts:
+    tol: float = 1e-6
+    maxit: int = 10000
+    retraction: int = 1
+    # RGBB warm start (Algorithm 1, first loop; stop rules of Sec. 7.1)
+    rgbb_tol: float = 1e-2
+    rgbb_maxit: int = 2000
+    rgbb_rho: float = 1e-4
+    rgbb_delta: float = 0.2
+    rgbb_varrho: float = 0.85
+    rgbb_step0: float = 0.1
+    # ARNT (Sec. 7.1 constants)
+    eta1: float = 0.01
+    eta2: float = 0.9
+    gamma0: float = 0.2
+    gamma1: float = 1.0
+    gamma2: float = 10.0
+    sigma_hat0: float = 1.0
+    rho: float = 1e-4
+    delta: float = 0.2
+    alpha0: float = 1.0
+    ls_max: int = 30
+    cg_maxit: int = 500
+    cg_T: float = 0.1
+    cg_theta: float = 1.0
+    max_reject_streak: int = 12
+
+
+@dataclass
+class SolveStats:
+    E: float = 0.0
+    gnorm: float = 0.0
+    rgbb_iters: int = 0
+    outer: int = 0
+    cg_total: int = 0
+    hvp_calls: int = 0
+    ls_trials: int = 0
+    rejected: int = 0
+    converged: bool = False
+    history: list = field(default_factory=list)
+
+
+def _norm(a):
+    return np.sqrt(inner(a, a))
+
+
+def energy_grad(prob, X):
+    LX = laplacian(prob, X)
+    return energy(prob, X, LX), egrad(prob, X, LX)
+
+
+def rgbb(prob, u, opts, stats):
+    """Riemannian gradient method with BB step and nonmonotone search (eq. NMN)."""
+    E, G = energy_grad(prob, u)
+    gR = rgrad(prob, u, G)[0]
+    gn = _norm(gR)
+    C, Q = E, 1.0
+    step = opts.rgbb_step0 / max(gn, 1e-300)
+    for k in range(opts.rgbb_maxit):
+        if gn <= opts.rgbb_tol:
+            break
+        eta = -gR
+        slope = inner(gR, eta)
+        t = step
+        for _ in range(opts.ls_max):
+            z = retract(prob, u, eta, t, opts.retraction)
+            Ez = energy(prob, z)
+            stats.ls_trials += 1
+            if Ez <= C + opts.rgbb_rho * t * slope:
+                break
+            t *= opts.rgbb_delta
+        Ez, Gz = energy_grad(prob, z)
+        gz = rgrad(prob, z, Gz)[0]
+        s = z - u
+        v = gz - gR
+        vv = inner(v, v)
+        step = abs(inner(s, v)) / vv if vv > 0 else step
+        step = min(max(step, 1e-20), 1e20)
+        Qn = opts.rgbb_varrho * Q + 1.0
+        C = (opts.rgbb_varrho * Q * C + Ez) / Qn
+        Q = Qn
+        u, E, gR, gn = z, Ez, gz, _norm(gz)
+        stats.rgbb_iters += 1
+    return u
+
+
+def tcg(prob, u, gR, ag, bg, sigma, opts, stats):
+    """Truncated CG on Hess m_k[xi] = -grad m_k.  Returns (s, d, A d, sigma_est)."""
+    gn = _norm(gR)
+    tol = min(opts.cg_T, gn ** opts.cg_theta) * gn
+    eps_c = 1e-12 * max(1.0, gn)
+    z = np.zeros_like(gR)
+    r = gR.copy()
+    p = -r
+    rr = inner(r, r)
+    for i in range(opts.cg_maxit):
+        Ap = rhess(prob, u, p, ag, bg, sigma)
+        stats.hvp_calls += 1
+        stats.cg_total += 1
+        kappa = inner(p, Ap)
+        pp = inner(p, p)
+        if kappa <= eps_c * pp:
+            s = -gR if i == 0 else z
+            if kappa < 0:
+                return s, p, Ap, abs(kappa) / pp
+            return s, None, None, None
+        alpha = rr / kappa
+        z = z + alpha * p
+        r = r + alpha * Ap
+        rr_new = inner(r, r)
+        if np.sqrt(rr_new) <= tol:
+            return z, None, None, None
+        p = -r + (rr_new / rr) * p
+        rr = rr_new
+    return z, None, None, None
+
+
+def arnt(prob, u, opts, stats):
+    """Modified adaptive regularized Newton method (Algorithm 1, second loop)."""
+    eps = np.finfo(float).eps
+    E, G = energy_grad(prob, u)
+    gR, G, ag, bg = rgrad(prob, u, G)
+    gn = _norm(gR)
+    shat = opts.sigma_hat0
+    streak = 0
+    for k in range(opts.maxit):
+        stats.history.append((E, gn))
+        if gn <= opts.tol:
+            stats.converged = True
+            break
+        if streak >= opts.max_reject_streak:
+            break                                   # stagnation below FP64 resolution
+        sigma = shat * gn
+        s, d, Ad, sest = tcg(prob, u, gR, ag, bg, sigma, opts, stats)
+        if d is not None:
+            tau = inner(d, gR) / inner(d, Ad)       # eq. xi
+            xi = s + tau * d
+        else:
+            xi = s
+        slope = inner(gR, xi)
+        t = opts.alpha0
+        ok = False
+        for _ in range(opts.ls_max):
+            z = retract(prob, u, xi, t, opts.retraction)
+            dz = z - u
+            m = inner(G, dz) + 0.5 * inner(ehvp(prob, u, dz), dz) + 0.5 * sigma * inner(dz, dz)
+            stats.hvp_calls += 1
+            stats.ls_trials += 1
+            if m <= opts.rho * t * slope:
+                ok = True
+                break
+            t *= opts.delta
+        ratio = -np.inf
+        if ok:
+            Ez, Gz = energy_grad(prob, z)
+            dE = Ez - E
+            if abs(dE) <= 16 * eps * abs(E) and abs(m) <= 16 * eps * abs(E):
+                ratio = 1.0
+            else:
+                ratio = dE / m
+        stats.outer += 1
+        if ratio >= opts.eta1:
+            u, E = z, Ez
+            gR, G, ag, bg = rgrad(prob, u, Gz)
+            gn = _norm(gR)
+            shat *= opts.gamma0 if ratio >= opts.eta2 else opts.gamma1
+            streak = 0
+        else:
+            stats.rejected += 1
+            streak += 1
+            shat *= opts.gamma2
+        if sest is not None and gn > 0:
+            shat = max(shat * gn, sest) / gn
+    stats.E, stats.gnorm = E, gn
+    return u
+
+
+def solve(prob, X0, opts=None):
+    """Ground state from X0 on one mesh: u0 = psi(X0) (projective), RGBB, ARNT."""
+    opts = opts or SolveOpts()
+    stats = SolveStats()
+    u = psi(prob, X0, 1)
+    u = rgbb(prob, u, opts, stats)
+    u = arnt(prob, u, opts, stats)
+    return u, stats
