@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the spin-F ground-state hot path on one MI355X.
+
+Workload: spin-3, 3D, 128^3 grid on [-8,8]^3, V = (x^2 + y^2 + 4 z^2)/2,
+beta = (500, 5, -5, 2), M = 0.2 (synthetic seeded inputs; no dataset).
+
+A step is one Riemannian Hessian-vector product of the regularised Newton
+model at a fixed point u, exactly as one truncated-CG iteration issues it:
+the three spectral-Laplacian axis passes, the pointwise spin-3 Hessian terms,
+the FP64 reductions for the tangent-space projection and <Z, HZ>, the
+projection, and the host read-back of <Z, HZ>.  The headline value is HVPs/s
+in mixed precision (c64 fields, FP64 reductions); the FP64 figure, both
+rooflines, time-to-ground-state for both precisions (full newton_solve:
+retraction, RGBB, ARNT, energies and gradients) and the CPU oracle timing
+ride on the same JSON line.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-solve] [--no-cpu]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=128, help="grid points per axis")
+    ap.add_argument("--no-solve", action="store_true", help="skip time-to-ground-state")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--solve-time", type=float, default=120.0, help="wall-clock cap per solve (s)")
+    ap.add_argument("--precisions", default="mixed,fp64")
+    return ap.parse_args()
+
+
+def kernel_bytes(kind, K, npts, cb, rb):
+    """Algorithmic HBM bytes of one launch of each HVP kernel kind:
+    cb = bytes per complex element, rb = bytes per real; one field = K*npts*cb."""
+    f = K * npts * cb
+    return {
+        "lap_axis_x": 2 * f,            # read Z, write T
+        "lap_axis_y": 3 * f,            # read Z and T, write T
+        "lap_axis_z": 3 * f,
+        "pw_hvp": 4 * f + npts * rb,    # read X, Z, LZ, V, write W
+        "project": 3 * f,               # read X and W, write out
+        "finalize": 0,
+    }.get(kind)
+
+
+def time_hvps(spec, prec, w, noise, steps, warmup, log):
+    import torch
+    from paper_1907_01194_amd.binding import Problem, R1
+    gp = Problem(spec, prec)
+    X = torch.from_numpy(w).cuda()
+    u = gp.retract(X, None, 0.0, R1)                       # u = psi(w), on the manifold
+    xi = gp.project(u, torch.from_numpy(noise).cuda())     # tangent direction
+    nrm = np.sqrt(gp.constraints(xi)[0])
+    xi /= nrm
+    gp.set_point(u)
+    Z = xi.to(gp.work_dtype).contiguous()
+    HZ = gp.empty(work=True)
+    for _ in range(warmup):
+        gp.hvp_dot(Z, 1e-2, out=HZ)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    gp.timing(True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    kappa = 0.0
+    for _ in range(steps):
+        _, kappa = gp.hvp_dot(Z, 1e-2, out=HZ)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    kt = gp.timing_read()
+    gp.timing(False)
+    log("%s: %.1f us per HVP (events), %.1f us (wall), kappa=%.6e" % (prec, 1e3 * ms, 1e6 * wall / steps, kappa))
+    for k, (c, t) in sorted(kt.items(), key=lambda x: -x[1][1]):
+        log("   %-12s %6d launches  %9.1f us avg" % (k, c, 1e3 * t / c))
+    del gp
+    torch.cuda.empty_cache()
+    return ms, kt
+
+
+def roofline(spec, prec, ms, kt):
+    K = spec.K
+    npts = int(np.prod(spec.n))
+    cb, rb = (16, 8) if prec == "fp64" else (8, 4)
+    # dominant kernel = largest total time among the HVP kernels
+    cand = {k: v for k, v in kt.items() if kernel_bytes(k, K, npts, cb, rb)}
+    dom = max(cand, key=lambda k: cand[k][1])
+    cnt, tot = cand[dom]
+    per_launch_s = tot / cnt / 1e3
+    b = kernel_bytes(dom, K, npts, cb, rb)
+    achieved = b / per_launch_s / 1e9
+    hvp_bytes = 3 * K * npts * cb + npts * rb             # read X, Z, V; write HZ
+    hvp_gbs = hvp_bytes / (ms / 1e3) / 1e9
+    return {
+        "kernel": {"bound": "hbm", "name": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                   "bytes_per_launch": b, "us_per_launch": round(per_launch_s * 1e6, 2)},
+        "hvp": {"bound": "hbm", "achieved": round(hvp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hvp_gbs / HBM_PEAK_GBS, 4), "compulsory_bytes": hvp_bytes,
+                "us_per_hvp": round(ms * 1e3, 2)},
+    }
+
+
+def time_solve(spec, prec, w, limit, log):
+    import torch
+    from paper_1907_01194_amd.binding import Problem
+    gp = Problem(spec, prec)
+    X = torch.from_numpy(w).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, st = gp.newton_solve(X, check=False, tol=1e-6, time_limit=limit)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("solve %s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
+        prec, st["E"], st["gnorm"], st["converged"], st["rgbb_iters"], st["outer"], st["cg_total"],
+        st["hvp_calls"], wall))
+    del gp
+    torch.cuda.empty_cache()
+    return {"seconds": round(wall, 3), "E": st["E"], "gnorm": st["gnorm"], "converged": bool(st["converged"]),
+            "rgbb_iters": st["rgbb_iters"], "outer": st["outer"], "cg_total": st["cg_total"],
+            "hvp_calls": st["hvp_calls"], "t_rgbb": round(st["t_rgbb"], 3), "t_arnt": round(st["t_arnt"], 3)}
+
+
+def cpu_baseline(spec, w, noise, log):
+    """The oracle (FP64, NumPy/scipy) per Riemannian HVP on the same workload."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import oracle
+    import oracle.energy as oe
+    oe.FFT_WORKERS = os.cpu_count()
+    prob = oracle.make_problem(spec.F, spec.n, spec.lo, spec.hi, spec.V, spec.beta, spec.M, spec.p, spec.q)
+    u = oracle.retraction.psi(prob, w, 1)
+    xi = oracle.project(prob, u, noise)
+    xi /= np.sqrt(oracle.inner(xi, xi))
+    ag, bg = oracle.proj_coeffs(prob, u, oracle.grad(prob, u))
+    oracle.rhess(prob, u, xi, ag, bg, 1e-2)                   # warm-up
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.rhess(prob, u, xi, ag, bg, 1e-2)
+    dt = (time.perf_counter() - t0) / reps
+    log("cpu oracle: %.2f s per HVP" % dt)
+    return {"value": round(1.0 / dt, 4), "unit": "HVP/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": "%d Riemannian HVPs (spin-3 128^3, FP64 NumPy/scipy.fft) after 1 warm-up, "
+                      "scipy.fft workers=%d" % (reps, os.cpu_count())}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the workload is one spin-3 128^3 grid; "
+              "--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    from paper_1907_01194_amd import workloads as W
+    spec = W.spin3_3d(args.n)
+    w = W.initial_state(spec, 3)
+    noise = W.random_direction(spec, 103)
+    precs = args.precisions.split(",")
+    res = {}
+    for prec in precs:
+        ms, kt = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
+        res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "roofline": roofline(spec, prec, ms, kt),
+                     "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()}}
+    solves = {}
+    if not args.no_solve:
+        for prec in precs:
+            solves[prec] = time_solve(spec, prec, w, args.solve_time, log)
+    cpu = None if args.no_cpu else cpu_baseline(spec, w, noise, log)
+    head = precs[0]
+    out = {
+        "metric": "HVPs/s + time-to-ground-state, spin-3 128^3, mixed vs FP64, same GPU",
+        "value": round(res[head]["hvp_per_s"], 2),
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res[head]["ms_per_hvp"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64-reductions" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "F": spec.F, "grid": list(spec.n), "box": [spec.lo[0], spec.hi[0]],
+                   "potential": "0.5*(x^2+y^2+4z^2)", "beta": list(spec.beta), "M": spec.M,
+                   "precision": head},
+        "roofline": res[head]["roofline"]["kernel"],
+        "hvp_roofline": res[head]["roofline"]["hvp"],
+        "cpu_baseline": cpu,
+        "precisions": {p: {"hvp_per_s": round(r["hvp_per_s"], 2), "ms_per_hvp": round(r["ms_per_hvp"], 4),
+                           "roofline": r["roofline"], "kernels_us": r["kernels_us"]} for p, r in res.items()},
+        "time_to_ground_state": solves or None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

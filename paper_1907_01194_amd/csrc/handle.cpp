@@ -1,0 +1,630 @@
+// C ABI entry points (include/gpe.h) and the device operations they are
+// built from.  Host code only: every kernel is launched through kernels.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+#include "runtime.h"
+
+static std::string g_create_error;
+
+namespace gpe {
+
+gpe_status fail(gpe_handle* h, gpe_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+gpe_status hip_fail(gpe_handle* h, hipError_t e, const char* where) {
+  std::string m = std::string("HIP error '") + hipGetErrorString(e) + "' in " + where;
+  return fail(h, e == hipErrorOutOfMemory ? GPE_ENOMEM : GPE_EHIP, m);
+}
+
+const char* const kKernelNames[KK_COUNT] = {"lap_axis_x", "lap_axis_y", "lap_axis_z", "pw_hvp",
+                                            "pw_grad", "finalize", "project", "comp_norms",
+                                            "scale_comps", "vector_ops"};
+
+hipEvent_t timing_event(gpe_handle* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+gpe_status alloc_field(gpe_handle* h, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(h, GPE_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return GPE_OK;
+}
+
+template <typename T>
+gpe_status laplacian(gpe_handle* h, const void* in, void* out) {
+  for (int a = 0; a < h->dim; ++a) GPE_KT(h, KK_LAP_X + a, lap_axis<T>(h->ax[a], in, a == 0 ? nullptr : out, out, h->st));
+  return GPE_OK;
+}
+template gpe_status laplacian<double>(gpe_handle*, const void*, void*);
+template gpe_status laplacian<float>(gpe_handle*, const void*, void*);
+
+gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout) {
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nq, h->res, post, h->F, gram, h->st));
+  GPE_HIP(h, hipMemcpyAsync(h->hres, h->res, sizeof(double) * nout, hipMemcpyDeviceToHost, h->st));
+  GPE_HIP(h, hipStreamSynchronize(h->st));
+  for (int i = 0; i < nout; ++i)
+    if (!std::isfinite(h->hres[i])) return fail(h, GPE_ENUMERIC, "NaN or Inf in a reduction");
+  return GPE_OK;
+}
+
+gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, double* E, double* ag, double* bg) {
+  GPE_TRY(laplacian<double>(h, X, h->T64));
+  GPE_KT(h, KK_PW_GRAD, pw_grad<double>(h->F, X, h->T64, h->V64, G, h->part, h->nblk, h->npts, h->pw, h->st));
+  const int nq = 1 + 2 * h->K;
+  if (G) {
+    GPE_TRY(reduce_to_host(h, nq, POST_GRAD, gram, nq + 2));
+    const double* r = h->hres;
+    double a11 = 0, a12 = 0, a22 = 0;
+    for (int i = 0; i < h->K; ++i) {
+      const double l = h->F - i;
+      a11 += r[1 + h->K + i];
+      a12 += l * r[1 + h->K + i];
+      a22 += l * l * r[1 + h->K + i];
+    }
+    if (!(a11 * a22 - a12 * a12 > 0))
+      return fail(h, GPE_EDEGEN, "degenerate point: u^T Gamma^2 u u^T u - (u^T Gamma u)^2 <= 0");
+    if (ag) *ag = r[nq];
+    if (bg) *bg = r[nq + 1];
+  } else {
+    GPE_TRY(reduce_to_host(h, nq, POST_NONE, nullptr, 1));
+  }
+  if (E) *E = h->hres[0];
+  return GPE_OK;
+}
+
+gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg,
+                        double* gnorm) {
+  h->hres[0] = ag;
+  h->hres[1] = bg;
+  // coefficients travel through res[40..41] on the device
+  GPE_HIP(h, hipMemcpyAsync(h->res + 40, h->hres, 2 * sizeof(double), hipMemcpyHostToDevice, h->st));
+  GPE_KT(h, KK_PROJECT, (project<double, double>(h->F, X, G, gR, h->res + 40, h->part, h->nblk, h->npts, h->st)));
+  GPE_TRY(reduce_to_host(h, 1, POST_NONE, nullptr, 1));
+  if (gnorm) *gnorm = std::sqrt(h->hres[0]);
+  return GPE_OK;
+}
+
+gpe_status adopt_point(gpe_handle* h) {
+  if (h->prec == GPE_MIXED) GPE_HIP(h, to_c64(h->Xp, h->Xp32, h->nel, h->st));
+  h->has_point = true;
+  return GPE_OK;
+}
+
+gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
+  if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
+  PwParams p = h->pw;
+  for (int i = 0; i < 7; ++i) p.zc[i] = (riem && i < h->K) ? sigma - h->alpha_g - h->beta_g * (h->F - i) : 0.0;
+  const int nq = 4 * h->K;
+  if (h->prec == GPE_FP64) {
+    GPE_TRY(laplacian<double>(h, Z, h->T64));
+    GPE_KT(h, KK_PW_HVP, pw_hvp<double>(h->F, h->Xp, Z, h->T64, h->V64, HZ, h->part, h->nblk, h->npts, p, h->st));
+  } else {
+    GPE_TRY(laplacian<float>(h, Z, h->T32));
+    GPE_KT(h, KK_PW_HVP, pw_hvp<float>(h->F, h->Xp32, Z, h->T32, h->V32, HZ, h->part, h->nblk, h->npts, p, h->st));
+  }
+  if (riem) {
+    GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nq, h->res, POST_HVP, h->F, h->gram_pt, h->st));
+    if (h->prec == GPE_FP64)
+      GPE_KT(h, KK_PROJECT, (project<double, double>(h->F, h->Xp, HZ, HZ, h->res + nq, nullptr, h->nblk, h->npts, h->st)));
+    else
+      GPE_KT(h, KK_PROJECT, (project<float, float>(h->F, h->Xp32, HZ, HZ, h->res + nq, nullptr, h->nblk, h->npts, h->st)));
+    if (kappa || zz) {
+      GPE_HIP(h, hipMemcpyAsync(h->hres, h->res + nq + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+      GPE_HIP(h, hipStreamSynchronize(h->st));
+      if (!std::isfinite(h->hres[0]) || !std::isfinite(h->hres[1]))
+        return fail(h, GPE_ENUMERIC, "NaN or Inf in the Hessian-vector product");
+      if (kappa) *kappa = h->hres[0];
+      if (zz) *zz = h->hres[1];
+    }
+  } else if (kappa || zz) {
+    GPE_TRY(reduce_to_host(h, nq, POST_NONE, nullptr, nq));
+    double k = 0, z2 = 0;
+    for (int i = 0; i < h->K; ++i) {
+      k += h->hres[2 * h->K + i];
+      z2 += h->hres[3 * h->K + i];
+    }
+    if (kappa) *kappa = k;
+    if (zz) *zz = z2;
+  }
+  return GPE_OK;
+}
+
+gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32, RetractNorms* rn) {
+  if (xi32)
+    GPE_KT(h, KK_NORMS, (comp_norms<double, float>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
+  else
+    GPE_KT(h, KK_NORMS, (comp_norms<double, double>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
+  const int K = h->K;
+  GPE_TRY(reduce_to_host(h, 3 * K, POST_NONE, nullptr, 3 * K));
+  for (int i = 0; i < K; ++i) {
+    rn->uu[i] = h->hres[i];
+    rn->ux[i] = xi ? h->hres[K + i] : 0.0;
+    rn->xx[i] = xi ? h->hres[2 * K + i] : 0.0;
+  }
+  return GPE_OK;
+}
+
+// Projective retraction (Sec. 6.1): sigma_l = 1/(sqrt(s)(1 - (l-M) r)) on
+// [f1, f2], r the zero of the increasing h1 on (1/(f1-M), 1/(f2-M)).
+static gpe_status sigma_projective(gpe_handle* h, const double* a, double* sig) {
+  const int K = h->K, F = h->F;
+  const double M = h->M;
+  int f1 = 1 << 20, f2 = -(1 << 20);
+  for (int i = 0; i < K; ++i)
+    if (a[i] > 0) {
+      const int l = F - i;
+      if (l < f1) f1 = l;
+      if (l > f2) f2 = l;
+    }
+  if (!(f1 < M && f2 > M)) return fail(h, GPE_EDOMAIN, "retraction argument outside Omega");
+  double lo = 1.0 / (f1 - M), hi = 1.0 / (f2 - M), t = 0.0;
+  for (int it = 0; it < 300; ++it) {
+    double f = 0.0, df = 0.0;
+    for (int i = 0; i < K; ++i) {
+      if (!(a[i] > 0)) continue;
+      const double c = (F - i) - M;
+      const double d = 1.0 - c * t;
+      f += c * a[i] / (d * d);
+      df += 2.0 * c * c * a[i] / (d * d * d);
+    }
+    if (f == 0.0) break;
+    if (f > 0) hi = t;
+    else lo = t;
+    double tn = t - f / df;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    const bool done = std::fabs(tn - t) <= 4e-16 * std::fmax(std::fabs(t), 1e-300);
+    t = tn;
+    if (done || hi - lo <= 4e-16 * std::fmax(std::fabs(lo), std::fabs(hi))) break;
+  }
+  double s = 0.0;
+  for (int i = 0; i < K; ++i) {
+    if (!(a[i] > 0)) continue;
+    const double d = 1.0 - ((F - i) - M) * t;
+    s += a[i] / (d * d);
+  }
+  const double rs = 1.0 / std::sqrt(s);
+  for (int i = 0; i < K; ++i) {
+    const int l = F - i;
+    sig[i] = (l >= f1 && l <= f2) ? rs / (1.0 - (l - M) * t) : 0.0;
+  }
+  return GPE_OK;
+}
+
+// Orthogonal retraction (Sec. 6.2): sigma_l = sqrt(r^l / sum_k a_k r^k), r the
+// positive zero of h2; searched as the sign change of sum (l-M) a_l e^{l s}.
+static gpe_status sigma_orthogonal(gpe_handle* h, const double* a, double* sig) {
+  const int K = h->K, F = h->F;
+  const double M = h->M;
+  double below = 0, above = 0;
+  for (int i = 0; i < K; ++i) {
+    if ((F - i) < M) below += a[i];
+    if ((F - i) > M) above += a[i];
+  }
+  if (!(below > 0 && above > 0)) return fail(h, GPE_EDOMAIN, "retraction argument outside Omega");
+  auto g = [&](double s) {
+    double mx = -1e300;
+    for (int i = 0; i < K; ++i) mx = std::fmax(mx, (F - i) * s);
+    double v = 0.0;
+    for (int i = 0; i < K; ++i) v += ((F - i) - M) * a[i] * std::exp((F - i) * s - mx);
+    return v;
+  };
+  double lo = -1.0, hi = 1.0;
+  while (g(lo) > 0 && lo > -1e6) lo *= 2;
+  while (g(hi) < 0 && hi < 1e6) hi *= 2;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (g(mid) > 0) hi = mid;
+    else lo = mid;
+  }
+  const double s = 0.5 * (lo + hi);
+  double den = 0.0;
+  for (int i = 0; i < K; ++i) den += a[i] * std::exp((F - i) * s);
+  for (int i = 0; i < K; ++i) sig[i] = std::sqrt(std::exp((F - i) * s) / den);
+  return GPE_OK;
+}
+
+// Closed-form retraction (Sec. 6.3, eq. retract3).
+static gpe_status sigma_closed(gpe_handle* h, const double* a, double* sig) {
+  const int K = h->K, F = h->F;
+  const double M = h->M;
+  double ww = 0, wg = 0, wg2 = 0;
+  for (int i = 0; i < K; ++i) {
+    const double l = F - i;
+    ww += a[i];
+    wg += l * a[i];
+    wg2 += l * l * a[i];
+  }
+  const double den = ww * wg2 - wg * wg;
+  auto num = [&](double l) { return wg2 - (M + l) * wg + M * l * ww; };
+  if (!(num(F) > 0 && num(-F) > 0 && den > 0)) return fail(h, GPE_EDOMAIN, "retraction argument outside S");
+  for (int i = 0; i < K; ++i) sig[i] = std::sqrt(num(F - i) / den);
+  return GPE_OK;
+}
+
+gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* sig) {
+  switch (kind) {
+    case GPE_R1_PROJECTIVE: return sigma_projective(h, a, sig);
+    case GPE_R2_ORTHOGONAL: return sigma_orthogonal(h, a, sig);
+    case GPE_R3_CLOSED: return sigma_closed(h, a, sig);
+    default: return fail(h, GPE_EINVAL, "unknown retraction kind");
+  }
+}
+
+gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32, double t,
+                         int kind, void* out) {
+  double a[7], sig[7];
+  for (int i = 0; i < h->K; ++i) {
+    a[i] = rn.uu[i] + 2.0 * t * rn.ux[i] + t * t * rn.xx[i];   // ||u_i + t xi_i||^2
+    if (a[i] < 0) a[i] = 0;
+  }
+  GPE_TRY(retraction_sigma(h, a, kind, sig));
+  if (xi32)
+    GPE_KT(h, KK_SCALE, (scale_comps<double, float, double>(h->K, u, xi, t, sig, out, h->npts, h->st)));
+  else
+    GPE_KT(h, KK_SCALE, (scale_comps<double, double, double>(h->K, u, xi, t, sig, out, h->npts, h->st)));
+  return GPE_OK;
+}
+
+gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out) {
+  if (!a32 && !b32) GPE_KT(h, KK_VECTOR, (dot<double, double>(a, b, h->part, h->nblk, n, h->st)));
+  else if (a32 && b32) GPE_KT(h, KK_VECTOR, (dot<float, float>(a, b, h->part, h->nblk, n, h->st)));
+  else if (!a32 && b32) GPE_KT(h, KK_VECTOR, (dot<double, float>(a, b, h->part, h->nblk, n, h->st)));
+  else GPE_KT(h, KK_VECTOR, (dot<double, float>(b, a, h->part, h->nblk, n, h->st)));
+  GPE_TRY(reduce_to_host(h, 1, POST_NONE, nullptr, 1));
+  *out = h->hres[0];
+  return GPE_OK;
+}
+
+}  // namespace gpe
+
+using namespace gpe;
+
+// ----------------------------------------------------------------- C ABI
+
+static bool factors_23(int n) {
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+extern "C" {
+
+const char* gpe_version(void) { return "gpe 0.1 (gfx950)"; }
+
+void gpe_solve_opts_default(gpe_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->maxit = 10000;
+  o->retraction = GPE_R1_PROJECTIVE;
+  o->rgbb_tol = 1e-2;
+  o->rgbb_maxit = 2000;
+  o->rgbb_rho = 1e-4;
+  o->rgbb_delta = 0.2;
+  o->rgbb_varrho = 0.85;
+  o->rgbb_step0 = 0.1;
+  o->eta1 = 0.01;
+  o->eta2 = 0.9;
+  o->gamma0 = 0.2;
+  o->gamma1 = 1.0;
+  o->gamma2 = 10.0;
+  o->sigma_hat0 = 1.0;
+  o->rho = 1e-4;
+  o->delta = 0.2;
+  o->alpha0 = 1.0;
+  o->ls_max = 30;
+  o->cg_maxit = 500;
+  o->cg_T = 0.1;
+  o->cg_theta = 1.0;
+  o->max_reject_streak = 12;
+  o->verbose = 0;
+  o->time_limit = 0.0;
+}
+
+const char* gpe_last_error(const gpe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+gpe_status gpe_destroy(gpe_handle* h) {
+  if (!h) return GPE_OK;
+  (void)hipSetDevice(h->device);
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  void* bufs[] = {h->V64, h->V32, h->part, h->res, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
+                  h->tw[0], h->tw[1], h->tw[2], h->tw[3], h->tw[4], h->tw[5]};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (void* b : h->solver_bufs)
+    if (b) (void)hipFree(b);
+  if (h->hres) (void)hipHostFree(h->hres);
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  delete h;
+  return GPE_OK;
+}
+
+gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision, void* stream, gpe_handle** out) {
+  if (!out) return fail(nullptr, GPE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pr || !V_host) return fail(nullptr, GPE_EINVAL, "problem or potential is NULL");
+  if (pr->F < 1 || pr->F > 3) return fail(nullptr, GPE_EINVAL, "F must be 1, 2 or 3");
+  if (pr->dim < 1 || pr->dim > 3) return fail(nullptr, GPE_EINVAL, "dim must be 1, 2 or 3");
+  if (precision != GPE_FP64 && precision != GPE_MIXED) return fail(nullptr, GPE_EINVAL, "bad precision");
+  if (!(std::fabs(pr->M) < pr->F)) return fail(nullptr, GPE_EINVAL, "|M| must be < F");
+  if (pr->M < 0) return fail(nullptr, GPE_EINVAL, "M < 0: reverse the component order and pass -M");
+  for (int a = 0; a < pr->dim; ++a) {
+    const int n = pr->n[a];
+    if (n < 4 || n % 2 || !factors_23(n) || !lap_size_supported(n))
+      return fail(nullptr, GPE_EINVAL, "n[" + std::to_string(a) + "] = " + std::to_string(n) +
+                                           " unsupported (even, factors 2 and 3 only, 4..512)");
+    if (!(pr->hi[a] > pr->lo[a])) return fail(nullptr, GPE_EINVAL, "empty box");
+  }
+  gpe_handle* h = new gpe_handle();
+  h->F = pr->F;
+  h->K = 2 * pr->F + 1;
+  h->dim = pr->dim;
+  h->prec = precision;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  h->p = pr->p;
+  h->q = pr->q;
+  h->M = pr->M;
+  for (int k = 0; k < 4; ++k) h->beta[k] = pr->beta[k];
+  if (h->F < 3) h->beta[3] = 0;
+  if (h->F < 2) h->beta[2] = 0;
+  h->npts = 1;
+  h->h = 1.0;
+  for (int a = 0; a < h->dim; ++a) {
+    h->n[a] = pr->n[a];
+    h->lo[a] = pr->lo[a];
+    h->hi[a] = pr->hi[a];
+    h->npts *= (size_t)pr->n[a];
+    h->h *= (pr->hi[a] - pr->lo[a]) / pr->n[a];
+  }
+  h->nel = h->npts * h->K;
+  (void)hipGetDevice(&h->device);
+
+  // pointwise constants
+  for (int i = 0; i < 7; ++i) {
+    const double l = h->F - i;
+    h->pw.zee[i] = i < h->K ? -h->p * l + h->q * l * l : 0.0;
+    h->pw.zc[i] = 0.0;
+  }
+  for (int k = 0; k < 4; ++k) {
+    h->pw.g[k] = 2.0 * h->beta[k] / h->h;
+    h->pw.e[k] = h->beta[k] / (2.0 * h->h);
+  }
+  h->nblk = red_blocks(h->npts);
+
+  gpe_status s;
+#define GPE_ALLOC(ptr, bytes)                                              \
+  do {                                                                     \
+    s = alloc_field(h, (void**)&(ptr), (bytes));                           \
+    if (s != GPE_OK) { g_create_error = h->err; gpe_destroy(h); return s; } \
+  } while (0)
+  const size_t f64 = h->nel * 16, f32 = h->nel * 8;
+  GPE_ALLOC(h->V64, h->npts * sizeof(double));
+  GPE_ALLOC(h->part, sizeof(double) * kMaxQ * kMaxRedBlocks);
+  GPE_ALLOC(h->res, sizeof(double) * 64);
+  GPE_ALLOC(h->gram_pt, sizeof(double) * 8);
+  GPE_ALLOC(h->gram_tmp, sizeof(double) * 8);
+  GPE_ALLOC(h->T64, f64);
+  GPE_ALLOC(h->Xp, f64);
+  GPE_ALLOC(h->Gp, f64);
+  if (precision == GPE_MIXED) {
+    GPE_ALLOC(h->V32, h->npts * sizeof(float));
+    GPE_ALLOC(h->T32, f32);
+    GPE_ALLOC(h->Xp32, f32);
+  }
+  if (hipHostMalloc((void**)&h->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
+    g_create_error = "pinned host allocation failed";
+    gpe_destroy(h);
+    return GPE_ENOMEM;
+  }
+  auto bail = [&](hipError_t e, const char* w) {
+    hip_fail(h, e, w);
+    g_create_error = h->err;
+    gpe_destroy(h);
+    return GPE_EHIP;
+  };
+  hipError_t e = hipMemcpyAsync(h->V64, V_host, h->npts * sizeof(double), hipMemcpyHostToDevice, h->st);
+  if (e != hipSuccess) return bail(e, "copy V");
+  if (precision == GPE_MIXED) {
+    std::vector<float> v32(h->npts);
+    for (size_t j = 0; j < h->npts; ++j) v32[j] = (float)V_host[j];
+    e = hipMemcpyAsync(h->V32, v32.data(), h->npts * sizeof(float), hipMemcpyHostToDevice, h->st);
+    if (e != hipSuccess) return bail(e, "copy V32");
+    e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return bail(e, "sync");
+  }
+  // Laplacian axes: axis a has lines of length n[a] at stride prod_{b<a} n[b]
+  size_t inner = 1;
+  for (int a = 0; a < h->dim; ++a) {
+    const int n = h->n[a];
+    LapAxis& ax = h->ax[a];
+    ax.n = n;
+    ax.inner = (int)inner;
+    ax.nlines = (long)(h->nel / n);
+    ax.lamc = 2.0 * M_PI / (h->hi[a] - h->lo[a]);
+    std::vector<double> t64(2 * n);
+    std::vector<float> t32(2 * n);
+    for (int m = 0; m < n; ++m) {
+      // exp(-2 pi i m / n), argument reduced exactly through m/n
+      const double ang = -2.0 * M_PI * (double)m / (double)n;
+      t64[2 * m] = std::cos(ang);
+      t64[2 * m + 1] = std::sin(ang);
+      t32[2 * m] = (float)t64[2 * m];
+      t32[2 * m + 1] = (float)t64[2 * m + 1];
+    }
+    GPE_ALLOC(h->tw[2 * a], n * 16);
+    GPE_ALLOC(h->tw[2 * a + 1], n * 8);
+    e = hipMemcpy(h->tw[2 * a], t64.data(), n * 16, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(e, "copy twiddles");
+    e = hipMemcpy(h->tw[2 * a + 1], t32.data(), n * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(e, "copy twiddles");
+    ax.tw64 = h->tw[2 * a];
+    ax.tw32 = h->tw[2 * a + 1];
+    inner *= (size_t)n;
+  }
+#undef GPE_ALLOC
+  e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) return bail(e, "sync");
+  *out = h;
+  return GPE_OK;
+}
+
+gpe_status gpe_energy(gpe_handle* h, const void* X, double* E) {
+  if (!h || !X || !E) return fail(h, GPE_EINVAL, "NULL argument");
+  return eval_point(h, X, nullptr, nullptr, E, nullptr, nullptr);
+}
+
+gpe_status gpe_grad(gpe_handle* h, const void* X, void* G, int riemannian, double* E, double* gnorm) {
+  if (!h || !X || !G) return fail(h, GPE_EINVAL, "NULL argument");
+  if (X == G) return fail(h, GPE_EINVAL, "X and G must be distinct");
+  double e, ag, bg;
+  GPE_TRY(eval_point(h, X, G, h->gram_tmp, &e, &ag, &bg));
+  if (E) *E = e;
+  if (riemannian) {
+    double gn;
+    GPE_TRY(project_grad(h, X, G, G, ag, bg, &gn));
+    if (gnorm) *gnorm = gn;
+  } else if (gnorm) {
+    double g2;
+    GPE_TRY(dot_host(h, G, false, G, false, h->nel, &g2));
+    *gnorm = std::sqrt(g2);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_set_point(gpe_handle* h, const void* X) {
+  if (!h || !X) return fail(h, GPE_EINVAL, "NULL argument");
+  GPE_HIP(h, hipMemcpyAsync(h->Xp, X, h->nel * 16, hipMemcpyDeviceToDevice, h->st));
+  GPE_TRY(eval_point(h, h->Xp, h->Gp, h->gram_pt, &h->E_pt, &h->alpha_g, &h->beta_g));
+  return adopt_point(h);
+}
+
+gpe_status gpe_hvp(gpe_handle* h, const void* Z, void* HZ, int riemannian, double sigma) {
+  if (!h || !Z || !HZ) return fail(h, GPE_EINVAL, "NULL argument");
+  if (Z == HZ) return fail(h, GPE_EINVAL, "Z and HZ must be distinct");
+  return hvp(h, Z, HZ, riemannian != 0, sigma, nullptr, nullptr);
+}
+
+gpe_status gpe_hvp_dot(gpe_handle* h, const void* Z, void* HZ, double sigma, double* kappa) {
+  if (!h || !Z || !HZ || !kappa) return fail(h, GPE_EINVAL, "NULL argument");
+  if (Z == HZ) return fail(h, GPE_EINVAL, "Z and HZ must be distinct");
+  return hvp(h, Z, HZ, true, sigma, kappa, nullptr);
+}
+
+gpe_status gpe_retract(gpe_handle* h, const void* X, const void* Xi, double t, int kind, void* Xout) {
+  if (!h || !X || !Xout) return fail(h, GPE_EINVAL, "NULL argument");
+  RetractNorms rn;
+  GPE_TRY(retract_norms(h, X, Xi, false, &rn));
+  GPE_TRY(retract_apply(h, rn, X, Xi, false, Xi ? t : 0.0, kind, Xout));
+  GPE_HIP(h, hipStreamSynchronize(h->st));
+  return GPE_OK;
+}
+
+gpe_status gpe_constraints(gpe_handle* h, const void* X, double* mass, double* mag) {
+  if (!h || !X) return fail(h, GPE_EINVAL, "NULL argument");
+  RetractNorms rn;
+  GPE_TRY(retract_norms(h, X, nullptr, false, &rn));
+  double m = 0, g = 0;
+  for (int i = 0; i < h->K; ++i) {
+    m += rn.uu[i];
+    g += (h->F - i) * rn.uu[i];
+  }
+  if (mass) *mass = m;
+  if (mag) *mag = g;
+  return GPE_OK;
+}
+
+gpe_status gpe_project(gpe_handle* h, const void* X, const void* W, void* out) {
+  if (!h || !X || !W || !out) return fail(h, GPE_EINVAL, "NULL argument");
+  RetractNorms rn;
+  GPE_TRY(retract_norms(h, X, W, false, &rn));
+  double a11 = 0, a12 = 0, a22 = 0, r1 = 0, r2 = 0;
+  for (int i = 0; i < h->K; ++i) {
+    const double l = h->F - i;
+    a11 += rn.uu[i];
+    a12 += l * rn.uu[i];
+    a22 += l * l * rn.uu[i];
+    r1 += rn.ux[i];
+    r2 += l * rn.ux[i];
+  }
+  const double det = a11 * a22 - a12 * a12;
+  if (!(det > 0)) return fail(h, GPE_EDEGEN, "degenerate Gram system in the projection");
+  const double alpha = (a22 * r1 - a12 * r2) / det, beta = (a11 * r2 - a12 * r1) / det;
+  double gn;
+  GPE_TRY(project_grad(h, X, W, out, alpha, beta, &gn));
+  return GPE_OK;
+}
+
+gpe_status gpe_timing_enable(gpe_handle* h, int enable) {
+  if (!h) return fail(h, GPE_EINVAL, "NULL handle");
+  GPE_HIP(h, hipStreamSynchronize(h->st));
+  for (auto& r : h->recs) {
+    h->event_pool.push_back(r.a);
+    h->event_pool.push_back(r.b);
+  }
+  h->recs.clear();
+  h->timing = enable != 0;
+  return GPE_OK;
+}
+
+gpe_status gpe_timing_read(gpe_handle* h, int max, const char** names, int* counts, double* ms, int* nkinds) {
+  if (!h) return fail(h, GPE_EINVAL, "NULL handle");
+  GPE_HIP(h, hipStreamSynchronize(h->st));
+  double tot[KK_COUNT] = {0};
+  int cnt[KK_COUNT] = {0};
+  for (auto& r : h->recs) {
+    float t = 0.f;
+    GPE_HIP(h, hipEventElapsedTime(&t, r.a, r.b));
+    tot[r.kind] += t;
+    cnt[r.kind] += 1;
+  }
+  int k = 0;
+  for (int i = 0; i < KK_COUNT; ++i) {
+    if (!cnt[i]) continue;
+    if (k < max) {
+      if (names) names[k] = kKernelNames[i];
+      if (counts) counts[k] = cnt[i];
+      if (ms) ms[k] = tot[i];
+    }
+    ++k;
+  }
+  if (nkinds) *nkinds = k;
+  return GPE_OK;
+}
+
+gpe_status gpe_newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* opts, gpe_solve_stats* stats) {
+  if (!h || !X) return fail(h, GPE_EINVAL, "NULL argument");
+  gpe_solve_opts o;
+  if (opts) o = *opts;
+  else gpe_solve_opts_default(&o);
+  gpe_solve_stats s;
+  std::memset(&s, 0, sizeof(s));
+  gpe_status r = newton_solve(h, X, &o, &s);
+  if (stats) *stats = s;
+  return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal launch interface between the host runtime (handle, solver) and the
+// HIP kernels.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace gpe {
+
+// One axis of the spectral Laplacian: lines of length n at stride `inner`,
+// nlines = K * npts / n of them; lamc = 2 pi / (hi - lo) of that axis;
+// twiddle tables exp(-2 pi i m / n), m = 0..n-1, in both precisions.
+struct LapAxis {
+  int n;
+  int inner;
+  long nlines;
+  double lamc;
+  const void* tw64;
+  const void* tw32;
+};
+
+template <typename T>
+hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st);
+bool lap_size_supported(int n);
+
+// Physical constants of the pointwise terms, already combined with h:
+// zee[l] = b_l (storage order), c0 = 2 beta0 / h, ... (gradient factors)
+// and e0 = beta0 / (2h), ... (energy factors).
+struct PwParams {
+  double zee[7];
+  double g[4];   // 2 beta_k / h
+  double e[4];   // beta_k / (2h)
+  double zc[7];  // HVP only: extra multiple of Z_i added to W_i
+};
+
+// Energy density (+ gradient).  Partials layout (nq = 1 + 2K):
+//   [0] sum of the energy density, [1+i] <X_i, G_i>, [1+K+i] ||X_i||^2.
+// G may be null (energy only; then [1+i] is 0).
+template <typename T>
+hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, double* part,
+                   int nblk, size_t npts, const PwParams& p, hipStream_t st);
+
+// Euclidean HVP pointwise part plus the Laplacian LZ already in LZ:
+//   W_i = LZ_i + (pointwise Hessian terms)_i + p.zc[i] Z_i.
+// Partials (nq = 4K): [i] <X_i, W_i>, [K+i] <X_i, Z_i>, [2K+i] <Z_i, W_i>, [3K+i] ||Z_i||^2.
+template <typename T>
+hipError_t pw_hvp(int F, const void* X, const void* Z, const void* LZ, const T* V, void* W,
+                  double* part, int nblk, size_t npts, const PwParams& p, hipStream_t st);
+
+// Post-processing done by the single-block finalize kernel after summing the
+// partial sums into res[0..nq).
+enum PostOp {
+  POST_NONE = 0,
+  // res = [e, <X_i,G_i>, ||X_i||^2]: writes alpha_g, beta_g to res[nq], res[nq+1]
+  // and copies ||X_i||^2 into gram[0..K).
+  POST_GRAD = 1,
+  // res = [<X_i,W_i>, <X_i,Z_i>, <Z_i,W_i>, ||Z_i||^2], gram = ||X_i||^2 of the point:
+  // writes alpha_w, beta_w, kappa = <Z, P W>, ||Z||^2 to res[nq .. nq+3].
+  POST_HVP = 2
+};
+hipError_t finalize(const double* part, int nblk, int nq, double* res, int post, int F,
+                    double* gram, hipStream_t st);
+
+// out_i = W_i - (coef[0] + coef[1] l_i) X_i (coef on the device).  X is c128
+// or c64 as TX; W/out in T.  If part != null, partial sums of ||out||^2 (nq = 1).
+template <typename T, typename TX>
+hipError_t project(int F, const void* X, const void* W, void* out, const double* coef,
+                   double* part, int nblk, size_t npts, hipStream_t st);
+
+// Per-component sums for the retraction: [i] ||u_i||^2, [K+i] <u_i, xi_i>,
+// [2K+i] ||xi_i||^2 (nq = 3K).  xi may be null (then only the first K are set).
+template <typename TU, typename TXI>
+hipError_t comp_norms(int K, const void* u, const void* xi, double* part, int nblk,
+                      size_t npts, hipStream_t st);
+
+// out_i = s_i (u_i + t xi_i), i = 0..K-1.  out may alias u.
+template <typename TU, typename TXI, typename TO>
+hipError_t scale_comps(int K, const void* u, const void* xi, double t, const double* s,
+                       void* out, size_t npts, hipStream_t st);
+
+// y = a x + b y (complex fields of n elements of type T, real scalars).
+template <typename T>
+hipError_t axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st);
+
+// z += a p; r += a q; partial sums of ||r||^2 (nq = 1).
+template <typename T>
+hipError_t cg_update(double a, const void* p, const void* q, void* z, void* r, double* part,
+                     int nblk, size_t n, hipStream_t st);
+
+// Partial sums of <a, b> = Re sum a conj(b) (nq = 1), a in TA, b in TB.
+template <typename TA, typename TB>
+hipError_t dot(const void* a, const void* b, double* part, int nblk, size_t n, hipStream_t st);
+
+// Precision conversion of complex fields.
+hipError_t to_c64(const void* src, void* dst, size_t n, hipStream_t st);
+hipError_t to_c128(const void* src, void* dst, size_t n, hipStream_t st);
+
+// out = a - b (complex fields) in T.
+template <typename TA, typename TB, typename TO>
+hipError_t diff(const void* a, const void* b, void* out, size_t n, hipStream_t st);
+
+}  // namespace gpe

@@ -1,0 +1,149 @@
+// Host runtime: the handle behind the C ABI and the device operations the
+// C entry points and the Newton driver are built from.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/gpe.h"
+#include "kernels.h"
+
+struct gpe_handle {
+  // problem (Sec. 2, Sec. 3)
+  int F = 0, K = 0, dim = 0;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  double beta[4] = {0, 0, 0, 0};
+  double p = 0, q = 0, M = 0;
+  size_t npts = 0;   // grid points
+  size_t nel = 0;    // K * npts complex elements per field
+  double h = 0;      // prod_a h_a
+  int prec = GPE_FP64;
+  hipStream_t st = nullptr;
+  int device = 0;
+
+  // device constants and scratch
+  double* V64 = nullptr;
+  float* V32 = nullptr;
+  gpe::LapAxis ax[3];
+  void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* part = nullptr;      // kMaxQ * kMaxRedBlocks
+  double* res = nullptr;       // 64 doubles
+  double* gram_pt = nullptr;   // ||u_i||^2 of the set point (7)
+  double* gram_tmp = nullptr;  // scratch gram (7)
+  double* hres = nullptr;      // pinned host mirror of res
+  int nblk = 1;
+  gpe::PwParams pw;
+
+  // owned fields
+  void* T64 = nullptr;   // Laplacian scratch, c128
+  void* T32 = nullptr;   // Laplacian scratch, c64 (mixed)
+  void* Xp = nullptr;    // set point, c128
+  void* Gp = nullptr;    // Euclidean gradient at the set point, c128
+  void* Xp32 = nullptr;  // c64 copy of the set point (mixed)
+  std::vector<void*> solver_bufs;  // lazily allocated by the Newton driver
+
+  // set-point state
+  bool has_point = false;
+  double E_pt = 0, alpha_g = 0, beta_g = 0;
+
+  // per-kernel event timing (gpe_timing_enable)
+  struct TimingRec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<TimingRec> recs;
+  std::vector<hipEvent_t> event_pool;
+
+  std::string err;
+};
+
+namespace gpe {
+
+// Status helpers: record a message on the handle and return the status.
+gpe_status fail(gpe_handle* h, gpe_status s, const std::string& msg);
+gpe_status hip_fail(gpe_handle* h, hipError_t e, const char* where);
+
+#define GPE_HIP(h, call)                                   \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return gpe::hip_fail(h, e_, #call); \
+  } while (0)
+
+// Kernel kinds of the timing record.
+enum KernelKind {
+  KK_LAP_X = 0, KK_LAP_Y, KK_LAP_Z, KK_PW_HVP, KK_PW_GRAD, KK_FINALIZE, KK_PROJECT, KK_NORMS,
+  KK_SCALE, KK_VECTOR, KK_COUNT
+};
+extern const char* const kKernelNames[KK_COUNT];
+hipEvent_t timing_event(gpe_handle* h);
+
+// Launch `call` (returning hipError_t) and, when timing is on, bracket it
+// with events on the handle's stream.
+#define GPE_KT(h, kind, call)                                           \
+  do {                                                                  \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                              \
+    if ((h)->timing) {                                                  \
+      a_ = gpe::timing_event(h);                                        \
+      b_ = gpe::timing_event(h);                                        \
+      (void)hipEventRecord(a_, (h)->st);                                \
+    }                                                                   \
+    hipError_t e_ = (call);                                             \
+    if ((h)->timing) {                                                  \
+      (void)hipEventRecord(b_, (h)->st);                                \
+      (h)->recs.push_back({(int)(kind), a_, b_});                       \
+    }                                                                   \
+    if (e_ != hipSuccess) return gpe::hip_fail(h, e_, #call);           \
+  } while (0)
+
+#define GPE_TRY(call)                  \
+  do {                                 \
+    gpe_status s_ = (call);            \
+    if (s_ != GPE_OK) return s_;       \
+  } while (0)
+
+gpe_status alloc_field(gpe_handle* h, void** p, size_t bytes);
+
+// out = L in (all axes), field precision T.
+template <typename T>
+gpe_status laplacian(gpe_handle* h, const void* in, void* out);
+
+// Reduce the last launch's partials (nq values, plus post-op) and copy
+// res[0..nout) to h->hres (synchronises).
+gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout);
+
+// Energy, gradient G (may be null), alpha_g/beta_g of G and ||X_i||^2 into gram.
+// Synchronises; fills *E, *ag, *bg.
+gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, double* E, double* ag,
+                      double* bg);
+
+// gR = P_X G with the multipliers (ag, bg) already known; returns ||gR||.
+gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg,
+                        double* gnorm);
+
+// Make (X, G, E, ag, bg, gram) the set point without recomputing anything.
+gpe_status adopt_point(gpe_handle* h);
+
+// HVP at the set point in the work precision; if kappa != null also
+// returns <Z, HZ> and ||Z||^2 (synchronises).
+gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, double* kappa,
+               double* zz);
+
+// Retraction in two steps: norms of u and xi (xi in the precision xi32 ? c64 : c128),
+// then the scaled combination for a given t.
+struct RetractNorms {
+  double uu[7], ux[7], xx[7];
+};
+gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32, RetractNorms* rn);
+gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32,
+                         double t, int kind, void* out);
+// Scalar part of the retractions (host, FP64): sigma_i from component norms a_i.
+gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* sig);
+
+// <a, b> with a c128 and b in (b32 ? c64 : c128), or both in the work precision.
+gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out);
+
+gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
+
+}  // namespace gpe

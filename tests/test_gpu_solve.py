@@ -1,0 +1,80 @@
+"""Solve-level parity of newton_solve (C ABI) with the oracle and with the
+paper's printed energies.  Parity is on the energy, the final gradient norm
+and the constraints, never on the raw wave function (the ground state is only
+defined up to phase and spin rotation)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_01194_amd import workloads as W
+from helpers import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_solve_spin1_1d_matches_oracle(torch):
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev
+    print("solve spin-1 1D 128", flush=True)
+    spec = W.spin1_1d()
+    X0 = W.initial_state(spec, 1)
+    u_or, st_or = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-8))
+    assert st_or.converged
+    gp = Problem(spec, "fp64")
+    X, st = gp.newton_solve(dev(X0), tol=1e-8)
+    assert st["converged"]
+    assert abs(st["E"] - st_or.E) <= 1e-10 * abs(st_or.E)
+    assert st["gnorm"] <= 1e-8
+    assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+
+
+def lattice1d(x):
+    return 0.5 * x * x + 25 * np.sin(np.pi * x / 4) ** 2
+
+
+@pytest.mark.parametrize("case,beta,box,n,M,E_paper", [
+    ("ferro", (130.6, -25.4, -125.3), 8, 256, 0.0, 10.3700300090),
+    ("nematic", (243, 12.1, -13), 16, 512, 0.5, 25.7372435384),
+    ("cyclic", (183.9, 26.8, 134.7), 16, 512, 1.5, 25.4639547287),
+])
+def test_solve_paper_table3_1(torch, case, beta, box, n, M, E_paper):
+    """Spin-2 1D ground states of Sec. 7.2, Table 3-1 (10-digit values)."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev
+    print("solve table 3-1", case, M, flush=True)
+    spec = W.make_spec("t31", 2, (n,), (-box,), (box,), lattice1d, beta, M)
+    X0 = W.paper_initial(spec, W.paper_U(2, case, M))
+    gp = Problem(spec, "fp64")
+    X, st = gp.newton_solve(dev(X0), tol=1e-7)
+    assert st["converged"]
+    assert abs(st["E"] - E_paper) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_spin2_2d_small(torch, prec):
+    """A 2D spin-2 solve (32^2, the spin-2 2D workload's physics on a coarser
+    grid, smooth initial data U phi_0 with a seeded spinor U) against the
+    oracle's ground-state energy."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev
+    print("solve spin-2 2D 32", prec, flush=True)
+    s = W.spin2_2d()
+    spec = W.make_spec("s2", 2, (32, 32), s.lo, s.hi, W.lattice(10.0, np.pi / 4), s.beta[:3], s.M)
+    X0 = W.paper_initial(spec, np.random.default_rng(0).random(5))
+    u_or, st_or = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-6))
+    gp = Problem(spec, prec)
+    X, st = gp.newton_solve(dev(X0), tol=1e-6)
+    assert st["converged"]
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert abs(st["E"] - st_or.E) <= tol * abs(st_or.E)
+    assert st["gnorm"] <= 1e-6
+    assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
