@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
     ap.add_argument("--no-solve", action="store_true", help="skip time-to-ground-state")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--solve-time", type=float, default=120.0, help="wall-clock cap per solve (s)")
+    ap.add_argument("--solve-time", type=float, default=45.0,
+                    help="wall-clock cap per solve of the benchmark physics (s)")
     ap.add_argument("--precisions", default="mixed,fp64")
     return ap.parse_args()
 
@@ -46,11 +47,10 @@ def kernel_bytes(kind, K, npts, cb, rb):
     cb = bytes per complex element, rb = bytes per real; one field = K*npts*cb."""
     f = K * npts * cb
     return {
-        "lap_axis_x": 2 * f,            # read Z, write T
-        "lap_axis_y": 3 * f,            # read Z and T, write T
-        "lap_axis_z": 3 * f,
-        "pw_hvp": 4 * f + npts * rb,    # read X, Z, LZ, V, write W
-        "project": 3 * f,               # read X and W, write out
+        "hvp_xpass": 4 * f + npts * rb,  # read X, Z, LX, V; write W
+        "lap_axis_y": 3 * f,             # read Z and W, write W
+        "lap_axis_z": 4 * f,             # read Z, W and X (projection), write HZ
+        "project": 3 * f,                # 1-D only: read X and W, write HZ
         "finalize": 0,
     }.get(kind)
 
@@ -117,6 +117,8 @@ def roofline(spec, prec, ms, kt):
 
 
 def time_solve(spec, prec, w, limit, log):
+    """Time-to-ground-state: newton_solve from w (device-resident before the
+    clock starts) to ||grad|| <= 1e-6, or until `limit` seconds."""
     import torch
     from paper_1907_01194_amd.binding import Problem
     gp = Problem(spec, prec)
@@ -126,8 +128,8 @@ def time_solve(spec, prec, w, limit, log):
     X, st = gp.newton_solve(X, check=False, tol=1e-6, time_limit=limit)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log("solve %s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
-        prec, st["E"], st["gnorm"], st["converged"], st["rgbb_iters"], st["outer"], st["cg_total"],
+    log("solve %s %s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
+        spec.name, prec, st["E"], st["gnorm"], st["converged"], st["rgbb_iters"], st["outer"], st["cg_total"],
         st["hvp_calls"], wall))
     del gp
     torch.cuda.empty_cache()
@@ -184,8 +186,26 @@ def main():
                      "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()}}
     solves = {}
     if not args.no_solve:
+        # (a) the paper's spin-3 128^3 workload (Sec. 7.3 Table 4-1 3D / Table 1-3-3,
+        #     Case II, M = 0.5) from the paper's initial data: converges
+        ps = W.spin3_3d_paper(args.n, "II", 0.5)
+        pw = W.paper_initial(ps, W.paper_U(3, None, ps.M, 0))
+        entry = {"workload": ps.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
+                 "paper_energy": 42.9822,
+                 "paper_context": {"seconds": 1050.1, "hardware": "MATLAB R2018b, 12-core Xeon E5-2680 v3",
+                                   "source": "Sec. 7.1 Table 1-3-3, ARNT with R1, M = 0.5, all meshes"}}
         for prec in precs:
-            solves[prec] = time_solve(spec, prec, w, args.solve_time, log)
+            entry[prec] = time_solve(ps, prec, pw, 300.0, log)
+            entry[prec]["energy_err_vs_paper"] = abs(entry[prec]["E"] - 42.9822)
+        solves["paper_case"] = entry
+        # (b) the benchmark physics (beta = (500, 5, -5, 2), gamma = (1, 1, 2)) from the same
+        #     kind of initial data, capped: its soft modes make the Newton iteration slow
+        bw = W.paper_initial(spec, W.paper_U(3, None, spec.M, 3))
+        entry = {"workload": spec.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
+                 "time_cap_s": args.solve_time}
+        for prec in precs:
+            entry[prec] = time_solve(spec, prec, bw, args.solve_time, log)
+        solves["benchmark_physics"] = entry
     cpu = None if args.no_cpu else cpu_baseline(spec, w, noise, log)
     head = precs[0]
     out = {

@@ -26,9 +26,12 @@ multiplied by gamma0 = 0.2 when rho_k >= eta2, by gamma1 = 1 when
 eta1 <= rho_k < eta2, by gamma2 = 10 on rejection.  RGBB: rho = 1e-4,
 delta = 0.2, varrho = 0.85, first step 0.1/||grad||, BB step clamped to
 [1e-20, 1e20].  Inner iterations capped at 500.  When both the energy change
-and the model value are below 16 eps |E| the ratio is taken as 1.  Twelve
-rejections in a row end the run unconverged (the tolerance lies below what
-FP64 energies resolve).
+and the model value are below 16 eps |E| neither can rank the two points: the
+trial is then accepted (ratio 1) if and only if it lowers the Riemannian
+gradient norm; and when the predicted decrease |<grad, xi>| is itself below
+16 eps |E| the Armijo search (whose model values are then rounding noise) is
+skipped and the full step alpha0 xi is tried.  Twelve rejections in a row end
+the run unconverged.
 """
 
 from dataclasses import dataclass, field
@@ -182,7 +185,10 @@ def arnt(prob, u, opts, stats):
         slope = inner(gR, xi)
         t = opts.alpha0
         ok = False
-        for _ in range(opts.ls_max):
+        # Near FP64 resolution the model and the energy cannot rank points: take
+        # the full step and let the gradient norm decide (reading, see header).
+        resolved = abs(slope) > 16 * eps * abs(E)
+        for _ in range(opts.ls_max if resolved else 0):
             z = retract(prob, u, xi, t, opts.retraction)
             dz = z - u
             m = inner(G, dz) + 0.5 * inner(ehvp(prob, u, dz), dz) + 0.5 * sigma * inner(dz, dz)
@@ -192,12 +198,17 @@ def arnt(prob, u, opts, stats):
                 ok = True
                 break
             t *= opts.delta
+        if not resolved:
+            z = retract(prob, u, xi, t, opts.retraction)
+            ok = True
+            m = 0.0
         ratio = -np.inf
         if ok:
             Ez, Gz = energy_grad(prob, z)
             dE = Ez - E
             if abs(dE) <= 16 * eps * abs(E) and abs(m) <= 16 * eps * abs(E):
-                ratio = 1.0
+                gz = rgrad(prob, z, Gz)[0]
+                ratio = 1.0 if np.sqrt(inner(gz, gz)) < gn else -np.inf
             else:
                 ratio = dE / m
         stats.outer += 1

@@ -11,63 +11,86 @@ namespace gpe {
 template <typename T> struct C7 { T v[7]; };
 
 // ----------------------------------------------------------------- finalize
-__global__ void __launch_bounds__(256)
-finalize_kernel(const double* __restrict__ part, int nblk, int nq, double* __restrict__ res, int post, int F,
-                double* gram) {
-  __shared__ double red[256 / kWave];
-  __shared__ double out[kMaxQ];
-  for (int q = 0; q < nq; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)q * nblk + b];
-    s = wave_sum(s);
-    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
-      out[q] = t;
-      res[q] = t;
-    }
-    __syncthreads();
+// One block per slot sums that slot's partials in a fixed order (so results
+// are bitwise reproducible); the last block to finish (counted with an atomic
+// ticket, which it resets) applies the post-operation.
+constexpr int kFinThreads = 256;
+
+__global__ void __launch_bounds__(kFinThreads)
+finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, int nq, double* __restrict__ res,
+                int post, int F, double* gram, unsigned int* ticket) {
+  __shared__ double red[kFinThreads / kWave];
+  __shared__ bool last;
+  const int q = blockIdx.x;
+  const double* pq = part + (size_t)q * stride;
+  const int n = nb.nb[q];
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int b = threadIdx.x;
+  for (; b + 3 * kFinThreads < n; b += 4 * kFinThreads) {
+    s0 += pq[b];
+    s1 += pq[b + kFinThreads];
+    s2 += pq[b + 2 * kFinThreads];
+    s3 += pq[b + 3 * kFinThreads];
   }
-  if (threadIdx.x != 0) return;
+  for (; b < n; b += kFinThreads) s0 += pq[b];
+  double s = wave_sum((s0 + s1) + (s2 + s3));
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kFinThreads / kWave; ++w) t += red[w];
+    res[q] = t;
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == (unsigned)(nq - 1);
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  *ticket = 0u;   // every block of this launch has taken its ticket
+  __threadfence();
+  const volatile double* out = res;
   const int K = 2 * F + 1;
-  if (post == POST_GRAD || post == POST_HVP) {
-    // Gram system of Lemma 4.1 (proof), with the measured u^T u, u^T G u, u^T G^2 u
-    const double* nrm = post == POST_GRAD ? out + 1 + K : gram;
-    const double* uw = post == POST_GRAD ? out + 1 : out;
+  if (post == POST_GRAD) {
+    // Gram system of Lemma 4.1 (proof) with the measured u^T u, u^T G u, u^T G^2 u
     double a11 = 0, a12 = 0, a22 = 0, r1 = 0, r2 = 0;
     for (int i = 0; i < K; ++i) {
-      const double l = F - i;
-      a11 += nrm[i];
-      a12 += l * nrm[i];
-      a22 += l * l * nrm[i];
-      r1 += uw[i];
-      r2 += l * uw[i];
+      const double l = F - i, nrm = out[1 + K + i];
+      a11 += nrm;
+      a12 += l * nrm;
+      a22 += l * l * nrm;
+      r1 += out[1 + i];
+      r2 += l * out[1 + i];
     }
     const double det = a11 * a22 - a12 * a12;
-    const double alpha = (a22 * r1 - a12 * r2) / det;
-    const double beta = (a11 * r2 - a12 * r1) / det;
-    res[nq] = alpha;
-    res[nq + 1] = beta;
-    if (post == POST_GRAD && gram)
-      for (int i = 0; i < K; ++i) gram[i] = nrm[i];
-    if (post == POST_HVP) {
-      double kappa = 0.0, zz = 0.0;
-      for (int i = 0; i < K; ++i) {
-        kappa += out[2 * K + i] - (alpha + beta * (F - i)) * out[K + i];
-        zz += out[3 * K + i];
-      }
-      res[nq + 2] = kappa;
-      res[nq + 3] = zz;
+    res[nq] = (a22 * r1 - a12 * r2) / det;
+    res[nq + 1] = (a11 * r2 - a12 * r1) / det;
+    if (gram)
+      for (int i = 0; i < K; ++i) gram[i] = out[1 + K + i];
+  } else if (post == POST_HVP_AB) {
+    double a11 = 0, a12 = 0, a22 = 0;
+    for (int i = 0; i < K; ++i) {
+      const double l = F - i;
+      a11 += gram[i];
+      a12 += l * gram[i];
+      a22 += l * l * gram[i];
     }
+    const double det = a11 * a22 - a12 * a12;
+    res[32] = (a22 * out[0] - a12 * out[1]) / det;
+    res[33] = (a11 * out[1] - a12 * out[0]) / det;
+  } else if (post == POST_HVP_KAPPA) {
+    double zlz = 0.0;
+    for (int k = 6; k < nq; ++k) zlz += out[k];
+    res[34] = out[4] + zlz - out[32] * out[2] - out[33] * out[3];
+    res[35] = out[5];
   }
 }
 
-hipError_t finalize(const double* part, int nblk, int nq, double* res, int post, int F, double* gram,
-                    hipStream_t st) {
-  if (nq > kMaxQ) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, part, nblk, nq, res, post, F, gram);
+hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post, int F,
+                    double* gram, unsigned int* ticket, hipStream_t st) {
+  if (nq < 1 || nq > kMaxQ || nq > (int)(sizeof(nb.nb) / sizeof(nb.nb[0]))) return hipErrorInvalidValue;
+  for (int q = 0; q < nq; ++q)
+    if (nb.nb[q] < 0 || (size_t)nb.nb[q] > stride) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nq), dim3(kFinThreads), 0, st, part, stride, nb, nq, res, post, F, gram,
+                     ticket);
   return hipGetLastError();
 }
 

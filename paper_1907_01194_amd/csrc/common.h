@@ -69,6 +69,28 @@ __device__ inline void block_partials(double (&acc)[NQ], double* __restrict__ pa
   }
 }
 
+// Same for any blockDim.x <= 1024 (a multiple of the wave size): block sums go
+// to part[q * stride + blk].
+template <int NQ>
+__device__ inline void block_partials_any(const double (&acc)[NQ], double* __restrict__ part, size_t stride,
+                                          size_t blk) {
+  __shared__ double red[1024 / kWave][NQ > 0 ? NQ : 1];
+  const int lane = threadIdx.x % kWave;
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double v = wave_sum(acc[q]);
+    if (lane == 0) red[wid][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+    part[(size_t)threadIdx.x * stride + blk] = s;
+  }
+}
+
 inline int red_blocks(size_t npts) {
   size_t b = (npts + kRedThreads * 4 - 1) / (kRedThreads * 4);
   if (b < 1) b = 1;

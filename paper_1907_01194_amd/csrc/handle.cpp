@@ -25,7 +25,7 @@ gpe_status hip_fail(gpe_handle* h, hipError_t e, const char* where) {
   return fail(h, e == hipErrorOutOfMemory ? GPE_ENOMEM : GPE_EHIP, m);
 }
 
-const char* const kKernelNames[KK_COUNT] = {"lap_axis_x", "lap_axis_y", "lap_axis_z", "pw_hvp",
+const char* const kKernelNames[KK_COUNT] = {"lap_axis_x", "lap_axis_y", "lap_axis_z", "hvp_xpass",
                                             "pw_grad", "finalize", "project", "comp_norms",
                                             "scale_comps", "vector_ops"};
 
@@ -59,7 +59,9 @@ template gpe_status laplacian<double>(gpe_handle*, const void*, void*);
 template gpe_status laplacian<float>(gpe_handle*, const void*, void*);
 
 gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout) {
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nq, h->res, post, h->F, gram, h->st));
+  SlotCounts nb;
+  for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = h->nblk;
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, h->ticket, h->st));
   GPE_HIP(h, hipMemcpyAsync(h->hres, h->res, sizeof(double) * nout, hipMemcpyDeviceToHost, h->st));
   GPE_HIP(h, hipStreamSynchronize(h->st));
   for (int i = 0; i < nout; ++i)
@@ -105,8 +107,46 @@ gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, d
 }
 
 gpe_status adopt_point(gpe_handle* h) {
-  if (h->prec == GPE_MIXED) GPE_HIP(h, to_c64(h->Xp, h->Xp32, h->nel, h->st));
+  // the HVP needs L X_p for <X_i, (LZ)_i> = <(LX)_i, Z_i>
+  if (h->prec == GPE_MIXED) {
+    GPE_HIP(h, to_c64(h->Xp, h->Xp32, h->nel, h->st));
+    GPE_TRY(laplacian<float>(h, h->Xp32, h->LX32));
+  } else {
+    GPE_TRY(laplacian<double>(h, h->Xp, h->LX64));
+  }
   h->has_point = true;
+  return GPE_OK;
+}
+
+template <typename T>
+static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const PwParams& p) {
+  const void* Xw = sizeof(T) == 8 ? h->Xp : h->Xp32;
+  const void* Yw = sizeof(T) == 8 ? h->LX64 : h->LX32;
+  const T* Vw = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h->V64 : (const void*)h->V32);
+  SlotCounts nb;
+  for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = 0;
+  int nbx = 0;
+  GPE_KT(h, KK_HVP_XPASS,
+         hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->st));
+  for (int q = 0; q < 7; ++q) nb.nb[q] = nbx;
+  double* coef = h->res + 32;
+  if (riem)
+    GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, h->st));
+  else
+    GPE_HIP(h, hipMemsetAsync(coef, 0, 2 * sizeof(double), h->st));
+  int nq = 7;
+  if (h->dim == 1) {
+    if (riem) GPE_KT(h, KK_PROJECT, (project<T, T>(h->F, Xw, HZ, HZ, coef, nullptr, h->nblk, h->npts, h->st)));
+  } else {
+    for (int a = 1; a < h->dim; ++a) {
+      const bool proj = riem && a == h->dim - 1;
+      GPE_KT(h, KK_LAP_X + a,
+             lap_axis_ex<T>(h->ax[a], Z, HZ, HZ, h->F, h->npts, proj ? Xw : nullptr, coef, h->part, h->pstride,
+                            6 + a, &nb.nb[6 + a], h->st));
+      nq = 7 + a;
+    }
+  }
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, POST_HVP_KAPPA, h->F, h->gram_pt, h->ticket, h->st));
   return GPE_OK;
 }
 
@@ -114,37 +154,15 @@ gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, 
   if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
   PwParams p = h->pw;
   for (int i = 0; i < 7; ++i) p.zc[i] = (riem && i < h->K) ? sigma - h->alpha_g - h->beta_g * (h->F - i) : 0.0;
-  const int nq = 4 * h->K;
-  if (h->prec == GPE_FP64) {
-    GPE_TRY(laplacian<double>(h, Z, h->T64));
-    GPE_KT(h, KK_PW_HVP, pw_hvp<double>(h->F, h->Xp, Z, h->T64, h->V64, HZ, h->part, h->nblk, h->npts, p, h->st));
-  } else {
-    GPE_TRY(laplacian<float>(h, Z, h->T32));
-    GPE_KT(h, KK_PW_HVP, pw_hvp<float>(h->F, h->Xp32, Z, h->T32, h->V32, HZ, h->part, h->nblk, h->npts, p, h->st));
-  }
-  if (riem) {
-    GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nq, h->res, POST_HVP, h->F, h->gram_pt, h->st));
-    if (h->prec == GPE_FP64)
-      GPE_KT(h, KK_PROJECT, (project<double, double>(h->F, h->Xp, HZ, HZ, h->res + nq, nullptr, h->nblk, h->npts, h->st)));
-    else
-      GPE_KT(h, KK_PROJECT, (project<float, float>(h->F, h->Xp32, HZ, HZ, h->res + nq, nullptr, h->nblk, h->npts, h->st)));
-    if (kappa || zz) {
-      GPE_HIP(h, hipMemcpyAsync(h->hres, h->res + nq + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-      GPE_HIP(h, hipStreamSynchronize(h->st));
-      if (!std::isfinite(h->hres[0]) || !std::isfinite(h->hres[1]))
-        return fail(h, GPE_ENUMERIC, "NaN or Inf in the Hessian-vector product");
-      if (kappa) *kappa = h->hres[0];
-      if (zz) *zz = h->hres[1];
-    }
-  } else if (kappa || zz) {
-    GPE_TRY(reduce_to_host(h, nq, POST_NONE, nullptr, nq));
-    double k = 0, z2 = 0;
-    for (int i = 0; i < h->K; ++i) {
-      k += h->hres[2 * h->K + i];
-      z2 += h->hres[3 * h->K + i];
-    }
-    if (kappa) *kappa = k;
-    if (zz) *zz = z2;
+  if (h->prec == GPE_FP64) GPE_TRY(hvp_t<double>(h, Z, HZ, riem, p));
+  else GPE_TRY(hvp_t<float>(h, Z, HZ, riem, p));
+  if (kappa || zz) {
+    GPE_HIP(h, hipMemcpyAsync(h->hres, h->res + 34, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    GPE_HIP(h, hipStreamSynchronize(h->st));
+    if (!std::isfinite(h->hres[0]) || !std::isfinite(h->hres[1]))
+      return fail(h, GPE_ENUMERIC, "NaN or Inf in the Hessian-vector product");
+    if (kappa) *kappa = h->hres[0];
+    if (zz) *zz = h->hres[1];
   }
   return GPE_OK;
 }
@@ -347,7 +365,8 @@ gpe_status gpe_destroy(gpe_handle* h) {
   if (!h) return GPE_OK;
   (void)hipSetDevice(h->device);
   if (h->st) (void)hipStreamSynchronize(h->st);
-  void* bufs[] = {h->V64, h->V32, h->part, h->res, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
+  void* bufs[] = {h->ticket, h->V64, h->V32, h->part, h->res, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
+                  h->LX64, h->LX32,
                   h->tw[0], h->tw[1], h->tw[2], h->tw[3], h->tw[4], h->tw[5]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -423,14 +442,31 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
   } while (0)
   const size_t f64 = h->nel * 16, f32 = h->nel * 8;
   GPE_ALLOC(h->V64, h->npts * sizeof(double));
-  GPE_ALLOC(h->part, sizeof(double) * kMaxQ * kMaxRedBlocks);
+  {
+    size_t ps = kMaxRedBlocks;
+    size_t inner = 1;
+    for (int a = 0; a < h->dim; ++a) {
+      LapAxis ax;
+      ax.n = pr->n[a];
+      ax.inner = (int)inner;
+      ax.nlines = (long)(h->nel / pr->n[a]);
+      const size_t m = lap_max_blocks(ax, h->K);
+      if (m > ps) ps = m;
+      inner *= (size_t)pr->n[a];
+    }
+    h->pstride = ps;
+  }
+  GPE_ALLOC(h->part, sizeof(double) * kMaxQ * h->pstride);
   GPE_ALLOC(h->res, sizeof(double) * 64);
   GPE_ALLOC(h->gram_pt, sizeof(double) * 8);
   GPE_ALLOC(h->gram_tmp, sizeof(double) * 8);
+  GPE_ALLOC(h->ticket, sizeof(unsigned int) * 4);
   GPE_ALLOC(h->T64, f64);
   GPE_ALLOC(h->Xp, f64);
   GPE_ALLOC(h->Gp, f64);
+  if (precision == GPE_FP64) GPE_ALLOC(h->LX64, f64);
   if (precision == GPE_MIXED) {
+    GPE_ALLOC(h->LX32, f32);
     GPE_ALLOC(h->V32, h->npts * sizeof(float));
     GPE_ALLOC(h->T32, f32);
     GPE_ALLOC(h->Xp32, f32);
@@ -446,7 +482,9 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     gpe_destroy(h);
     return GPE_EHIP;
   };
-  hipError_t e = hipMemcpyAsync(h->V64, V_host, h->npts * sizeof(double), hipMemcpyHostToDevice, h->st);
+  hipError_t e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int) * 4, h->st);
+  if (e != hipSuccess) return bail(e, "clear ticket");
+  e = hipMemcpyAsync(h->V64, V_host, h->npts * sizeof(double), hipMemcpyHostToDevice, h->st);
   if (e != hipSuccess) return bail(e, "copy V");
   if (precision == GPE_MIXED) {
     std::vector<float> v32(h->npts);

@@ -40,12 +40,25 @@ template <typename T>
 hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, double* part,
                    int nblk, size_t npts, const PwParams& p, hipStream_t st);
 
-// Euclidean HVP pointwise part plus the Laplacian LZ already in LZ:
-//   W_i = LZ_i + (pointwise Hessian terms)_i + p.zc[i] Z_i.
-// Partials (nq = 4K): [i] <X_i, W_i>, [K+i] <X_i, Z_i>, [2K+i] <Z_i, W_i>, [3K+i] ||Z_i||^2.
+// Fused x-axis pass of the HVP (all components of RPB x-rows per workgroup):
+//   W = L_x Z + (pointwise Hessian terms of Sec. 3) + p.zc[i] Z_i,
+// with FP64 partial sums (one per workgroup, slots of stride `stride`):
+//   [0] sum_i <X_i, W_i>  [1] sum_i l_i <X_i, W_i>  (both through <(LX)_i, Z_i> = <X_i, (LZ)_i>,
+//   Y = L X), [2] sum <X_i,Z_i>, [3] sum l_i <X_i,Z_i>, [4] <Z, W - LZ>, [5] ||Z||^2,
+//   [6] <Z, L_x Z> (Parseval).
+// Returns the number of workgroups (partials per slot) in *nblk_out.
 template <typename T>
-hipError_t pw_hvp(int F, const void* X, const void* Z, const void* LZ, const T* V, void* W,
-                  double* part, int nblk, size_t npts, const PwParams& p, hipStream_t st);
+hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
+                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nblk_out,
+                     hipStream_t st);
+
+// Axis pass with Parseval partial <Z, L_a Z> into part[slot * stride + wg] and,
+// if coef != null, the projection epilogue out -= (coef[0] + coef[1] l) X.
+template <typename T>
+hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
+                       const void* X, const double* coef, double* part, size_t stride, int slot, int* nblk_out,
+                       hipStream_t st);
+size_t lap_max_blocks(const LapAxis& ax, int K);
 
 // Post-processing done by the single-block finalize kernel after summing the
 // partial sums into res[0..nq).
@@ -54,12 +67,22 @@ enum PostOp {
   // res = [e, <X_i,G_i>, ||X_i||^2]: writes alpha_g, beta_g to res[nq], res[nq+1]
   // and copies ||X_i||^2 into gram[0..K).
   POST_GRAD = 1,
-  // res = [<X_i,W_i>, <X_i,Z_i>, <Z_i,W_i>, ||Z_i||^2], gram = ||X_i||^2 of the point:
-  // writes alpha_w, beta_w, kappa = <Z, P W>, ||Z||^2 to res[nq .. nq+3].
-  POST_HVP = 2
+  // res = HVP slots 0..6 (see hvp_xpass), gram = ||X_i||^2 of the point:
+  // writes the projection coefficients alpha_w, beta_w to res[32], res[33].
+  POST_HVP_AB = 2,
+  // res = HVP slots 0..8 (x, y, z Parseval in 6, 7, 8), projection
+  // coefficients in res[32..33] (zero for a Euclidean HVP):
+  // writes kappa = <Z, HZ> to res[34] and ||Z||^2 to res[35].
+  POST_HVP_KAPPA = 3
 };
-hipError_t finalize(const double* part, int nblk, int nq, double* res, int post, int F,
-                    double* gram, hipStream_t st);
+struct SlotCounts {
+  int nb[32];   // kMaxQ
+};
+// Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
+// (deterministic), then apply `post`.  ticket: a device counter that is 0
+// between launches (the launch leaves it at 0).
+hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post,
+                    int F, double* gram, unsigned int* ticket, hipStream_t st);
 
 // out_i = W_i - (coef[0] + coef[1] l_i) X_i (coef on the device).  X is c128
 // or c64 as TX; W/out in T.  If part != null, partial sums of ||out||^2 (nq = 1).

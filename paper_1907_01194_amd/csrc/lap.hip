@@ -13,6 +13,7 @@
 // LPB at a time at consecutive x so that every global access is coalesced.
 #include "common.h"
 #include "kernels.h"
+#include "spin.h"
 
 namespace gpe {
 
@@ -126,10 +127,17 @@ struct LineCtx {
   bool valid;       // line exists
 };
 
+// Epilogue of the last inverse pass: out = acc + val - pc * X (pc = 0: no projection).
+template <typename T> struct Epi {
+  const c_t<T>* acc;
+  const c_t<T>* X;
+  T pc;
+};
+
 template <typename T, int N, int s, bool FWD, int SRC, int DST>
 __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* lds,
                                       const c_t<T>* tw, c_t<T>* __restrict__ gout,
-                                      const c_t<T>* gacc, const LineCtx& lc, T lamc, T invn) {
+                                      const Epi<T>& epi, const LineCtx& lc, T lamc, T invn, double& pars) {
   using T2 = c_t<T>;
   constexpr RadixPlan P = Geo<N>::P;
   constexpr int R = P.r[s];
@@ -173,13 +181,21 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
         if (LAST_FWD) {
           const int p = idx < N / 2 ? idx : idx - N;
           const T lam = lamc * (T)p;
-          val = cscale(val, lam * lam * invn);
+          const T sc = lam * lam * invn;
+          pars += (double)sc * (double)cabs2(val);   // Parseval: <Z, L_a Z> = sum lambda^2/n |Z^|^2
+          val = cscale(val, sc);
         }
         if (DST == DST_LDS) {
           lds[lc.lbase + idx * lc.lstride] = val;
         } else {
           const size_t g = lc.goff + (size_t)idx * lc.gstride;
-          gout[g] = gacc ? cadd(gacc[g], val) : val;
+          T2 o = epi.acc ? cadd(epi.acc[g], val) : val;
+          if (epi.X) {
+            const T2 xv = epi.X[g];
+            o.x -= epi.pc * xv.x;
+            o.y -= epi.pc * xv.y;
+          }
+          gout[g] = o;
         }
       }
     }
@@ -189,34 +205,44 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
 
 template <typename T, int N, int s>
 __device__ __forceinline__ void fwd_stages(const c_t<T>* gin, c_t<T>* lds, const c_t<T>* tw,
-                                           const LineCtx& lc, T lamc, T invn) {
+                                           const LineCtx& lc, T lamc, T invn, double& pars) {
   constexpr int S = Geo<N>::P.S;
+  const Epi<T> none{nullptr, nullptr, T(0)};
   if constexpr (s < S) {
     if constexpr (s == 0)
-      stage<T, N, 0, true, SRC_GLOBAL, DST_LDS>(gin, lds, tw, nullptr, nullptr, lc, lamc, invn);
+      stage<T, N, 0, true, SRC_GLOBAL, DST_LDS>(gin, lds, tw, nullptr, none, lc, lamc, invn, pars);
     else
-      stage<T, N, s, true, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, nullptr, lc, lamc, invn);
-    fwd_stages<T, N, s + 1>(gin, lds, tw, lc, lamc, invn);
+      stage<T, N, s, true, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, lamc, invn, pars);
+    fwd_stages<T, N, s + 1>(gin, lds, tw, lc, lamc, invn, pars);
   }
 }
 
-template <typename T, int N, int s>
-__device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>* gout,
-                                           const c_t<T>* gacc, const LineCtx& lc) {
+// LAST_TO_GLOBAL: the last inverse pass writes global memory through the
+// epilogue; otherwise it writes the result back to LDS.
+template <typename T, int N, int s, bool LAST_TO_GLOBAL>
+__device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>* gout, const Epi<T>& epi,
+                                           const LineCtx& lc) {
   constexpr int S = Geo<N>::P.S;
+  const Epi<T> none{nullptr, nullptr, T(0)};
+  double dummy = 0.0;
   if constexpr (s < S) {
-    if constexpr (s == S - 1)
-      stage<T, N, s, false, SRC_LDS, DST_GLOBAL>(nullptr, lds, tw, gout, gacc, lc, T(0), T(0));
+    if constexpr (s == S - 1 && LAST_TO_GLOBAL)
+      stage<T, N, s, false, SRC_LDS, DST_GLOBAL>(nullptr, lds, tw, gout, epi, lc, T(0), T(0), dummy);
     else
-      stage<T, N, s, false, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, nullptr, lc, T(0), T(0));
-    inv_stages<T, N, s + 1>(lds, tw, gout, gacc, lc);
+      stage<T, N, s, false, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, T(0), T(0), dummy);
+    inv_stages<T, N, s + 1, LAST_TO_GLOBAL>(lds, tw, gout, epi, lc);
   }
 }
 
+// One axis pass for every line of every component: out = acc + L_a(in)
+// [- (coef[0] + coef[1] l) X], with the Parseval sum <in, L_a in> per workgroup
+// in part[slot * stride + wg] when part != null.
 template <typename T, int N>
 __global__ void __launch_bounds__(Geo<N>::THREADS)
 lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
-                const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc) {
+                const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F, size_t npts,
+                const c_t<T>* __restrict__ X, const double* __restrict__ coef, double* __restrict__ part,
+                size_t stride, int slot) {
   using T2 = c_t<T>;
   constexpr int TPL = Geo<N>::TPL;
   constexpr int LPB = Geo<N>::LPB;
@@ -247,14 +273,142 @@ lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
   lc.goff = (size_t)o * N * inner + i;
   lc.gstride = inner;
   const T invn = T(1) / T(N);
+  Epi<T> epi{acc, nullptr, T(0)};
+  if (X && lc.valid) {
+    const int comp = (int)(lc.goff / npts);          // a line never crosses a component
+    epi.X = X;
+    epi.pc = (T)(coef[0] + coef[1] * (double)(F - comp));
+  }
+  double pars = 0.0;
   // Stage 0 reads global memory and uses no twiddles; the barrier that ends it
   // also publishes the twiddle table.
-  fwd_stages<T, N, 0>(in, lds, tw, lc, lamc, invn);
-  inv_stages<T, N, 0>(lds, tw, out, acc, lc);
+  fwd_stages<T, N, 0>(in, lds, tw, lc, lamc, invn, pars);
+  inv_stages<T, N, 0, true>(lds, tw, out, epi, lc);
+  if (part) {
+    double a[1] = {pars};
+    block_partials_any<1>(a, part + (size_t)slot * stride, 0, blockIdx.x);
+  }
+}
+
+// Fused x pass of the Hessian-vector product: RPB x-rows, all K components.
+template <int N, int K> struct XGeo {
+  static constexpr int TPL = Geo<N>::TPL;
+  static constexpr int R0 = 256 / (K * TPL);
+  static constexpr int RPB = R0 >= 16 ? 16 : R0 >= 8 ? 8 : R0 >= 4 ? 4 : R0 >= 2 ? 2 : 1;
+  static constexpr int LINES = RPB * K;
+  static constexpr int THREADS = ((LINES * TPL + 63) / 64) * 64;
+};
+
+template <typename T, int N, int F>
+__global__ void __launch_bounds__((XGeo<N, 2 * F + 1>::THREADS))
+hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, const c_t<T>* __restrict__ Y,
+                 const T* __restrict__ V, c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
+                 size_t npts, T lamc, PwParams p, double* __restrict__ part, size_t stride) {
+  using T2 = c_t<T>;
+  constexpr int K = 2 * F + 1;
+  constexpr int TPL = Geo<N>::TPL;
+  constexpr int RPB = XGeo<N, K>::RPB;
+  constexpr int LINES = XGeo<N, K>::LINES;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* tw = reinterpret_cast<T2*>(smem_raw);
+  T2* lds = tw + N;
+  const int t = threadIdx.x;
+  for (int m = t; m < N; m += blockDim.x) tw[m] = twg[m];
+  const long row0 = (long)blockIdx.x * RPB;
+
+  // ---- c64: prefetch the pointwise operands of this thread's first point so
+  // their latency hides behind the transforms below (in FP64 the extra live
+  // registers would cost more occupancy than the overlap gains)
+  constexpr bool kPrefetch = sizeof(T) == 4;
+  int pt = t;
+  bool have = pt < RPB * N && row0 + pt / N < nrows;
+  T2 x[K], z[K], y[K];
+  T vj = T(0);
+  size_t j = have ? (size_t)(row0 + pt / N) * N + pt % N : 0;
+  auto load_point = [&]() {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      x[i] = X[i * npts + j];
+      z[i] = Z[i * npts + j];
+      y[i] = Y[i * npts + j];
+    }
+    vj = V[j];
+  };
+  if (kPrefetch && have) load_point();
+
+  // ---- L_x Z for the RPB rows of every component, left in LDS
+  LineCtx lc;
+  const int ls = t / TPL;                 // line slot = comp * RPB + row
+  lc.tl = t % TPL;
+  const int comp = ls / RPB, r = ls % RPB;
+  lc.valid = ls < LINES && row0 + r < nrows;
+  lc.goff = (size_t)comp * npts + (size_t)(row0 + r) * N;
+  lc.gstride = 1;
+  lc.lbase = ls * (N + 1);
+  lc.lstride = 1;
+  const T invn = T(1) / T(N);
+  double pars = 0.0;
+  const Epi<T> none{nullptr, nullptr, T(0)};
+  fwd_stages<T, N, 0>(Z, lds, tw, lc, lamc, invn, pars);
+  inv_stages<T, N, 0, false>(lds, tw, nullptr, none, lc);
+
+  // ---- pointwise Hessian terms, W = L_x Z + q
+  T zcoef[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) zcoef[i] = (T)p.zc[i];
+  double acc[7] = {0, 0, 0, 0, 0, 0, pars};
+  auto point = [&](int rr, int xx) {
+    double xy = 0, lxy = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double c = (double)cdotr(y[i], z[i]);     // <(LX)_i, Z_i> = <X_i, (LZ)_i>
+      xy += c;
+      lxy += (double)(F - i) * c;
+    }
+    T2 q[K];
+    hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) { q[i] = qi; });
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const T2 lz = lds[(i * RPB + rr) * (N + 1) + xx];
+      W[i * npts + j] = cadd(lz, q[i]);
+      const double xq = (double)cdotr(x[i], q[i]);
+      const double xz = (double)cdotr(x[i], z[i]);
+      const double l = (double)(F - i);
+      xy += xq;
+      lxy += l * xq;
+      acc[2] += xz;
+      acc[3] += l * xz;
+      acc[4] += (double)cdotr(z[i], q[i]);
+      acc[5] += (double)cabs2(z[i]);
+    }
+    acc[0] += xy;
+    acc[1] += lxy;
+  };
+  if constexpr (kPrefetch) {
+    while (have) {
+      point(pt / N, pt % N);
+      pt += blockDim.x;
+      have = pt < RPB * N && row0 + pt / N < nrows;
+      if (have) {
+        j = (size_t)(row0 + pt / N) * N + pt % N;
+        load_point();
+      }
+    }
+  } else {
+    for (pt = t; pt < RPB * N; pt += blockDim.x) {
+      if (row0 + pt / N >= nrows) break;
+      j = (size_t)(row0 + pt / N) * N + pt % N;
+      load_point();
+      point(pt / N, pt % N);
+    }
+  }
+  block_partials_any<7>(acc, part, stride, blockIdx.x);
 }
 
 template <typename T, int N>
-static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st) {
+static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
+                       const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
+                       hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int LPB = Geo<N>::LPB;
   const long nlines = ax.nlines;
@@ -263,20 +417,89 @@ static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void*
   const T2* tw = reinterpret_cast<const T2*>(sizeof(T) == 8 ? ax.tw64 : ax.tw32);
   hipLaunchKernelGGL((lap_axis_kernel<T, N>), dim3(grid), dim3(Geo<N>::THREADS), lds, st,
                      reinterpret_cast<const T2*>(in), reinterpret_cast<const T2*>(acc),
-                     reinterpret_cast<T2*>(out), tw, nlines, ax.inner, (T)ax.lamc);
+                     reinterpret_cast<T2*>(out), tw, nlines, ax.inner, (T)ax.lamc, F, npts,
+                     reinterpret_cast<const T2*>(X), coef, part, stride, slot);
+  if (nb) *nb = grid;
 }
+
+#define GPE_SIZES(M) M(4) M(6) M(8) M(12) M(16) M(24) M(32) M(48) M(64) M(96) M(128) M(192) M(256) M(384) M(512)
 
 template <typename T>
 hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st) {
   switch (ax.n) {
-#define GPE_CASE(NN) case NN: launch_lap<T, NN>(ax, in, acc, out, st); break;
-    GPE_CASE(4) GPE_CASE(6) GPE_CASE(8) GPE_CASE(12) GPE_CASE(16) GPE_CASE(24) GPE_CASE(32)
-    GPE_CASE(48) GPE_CASE(64) GPE_CASE(96) GPE_CASE(128) GPE_CASE(192) GPE_CASE(256)
-    GPE_CASE(384) GPE_CASE(512)
+#define GPE_CASE(NN) \
+  case NN: launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, st); break;
+    GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
+                       const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
+                       hipStream_t st) {
+  switch (ax.n) {
+#define GPE_CASE(NN) \
+  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, st); break;
+    GPE_SIZES(GPE_CASE)
+#undef GPE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N, int F>
+static void launch_xpass(const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y, const T* V,
+                         void* W, const PwParams& p, double* part, size_t stride, int* nb, hipStream_t st) {
+  using T2 = c_t<T>;
+  constexpr int K = 2 * F + 1;
+  using G = XGeo<N, K>;
+  const long nrows = (long)(npts / N);
+  const int grid = (int)((nrows + G::RPB - 1) / G::RPB);
+  const size_t lds = sizeof(T2) * (size_t)(N + G::LINES * (N + 1));
+  const T2* tw = reinterpret_cast<const T2*>(sizeof(T) == 8 ? ax.tw64 : ax.tw32);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hvp_xpass_kernel<T, N, F>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((hvp_xpass_kernel<T, N, F>), dim3(grid), dim3(G::THREADS), lds, st,
+                     reinterpret_cast<const T2*>(X), reinterpret_cast<const T2*>(Z),
+                     reinterpret_cast<const T2*>(Y), V, reinterpret_cast<T2*>(W), tw, nrows, npts, (T)ax.lamc, p,
+                     part, stride);
+  *nb = grid;
+}
+
+template <typename T>
+hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
+                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb,
+                     hipStream_t st) {
+  switch (ax.n * 4 + F) {
+#define GPE_CASE(NN)                                                                                  \
+  case NN * 4 + 1: launch_xpass<T, NN, 1>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
+  case NN * 4 + 2: launch_xpass<T, NN, 2>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
+  case NN * 4 + 3: launch_xpass<T, NN, 3>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break;
+    GPE_SIZES(GPE_CASE)
+#undef GPE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t lap_max_blocks(const LapAxis& ax, int K) {
+  size_t lpb = 1, rpb = 1;
+  switch (ax.n) {
+#define GPE_CASE(NN)                                                                       \
+  case NN:                                                                                 \
+    lpb = Geo<NN>::LPB;                                                                    \
+    rpb = K == 3 ? XGeo<NN, 3>::RPB : K == 5 ? XGeo<NN, 5>::RPB : XGeo<NN, 7>::RPB;       \
+    break;
+    GPE_SIZES(GPE_CASE)
+#undef GPE_CASE
+  }
+  const size_t a = (ax.nlines + lpb - 1) / lpb;
+  const size_t b = ((size_t)ax.nlines / K + rpb - 1) / rpb;
+  return a > b ? a : b;
 }
 
 bool lap_size_supported(int n) {
@@ -289,5 +512,13 @@ bool lap_size_supported(int n) {
 
 template hipError_t lap_axis<double>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis<float>(const LapAxis&, const void*, const void*, void*, hipStream_t);
+template hipError_t lap_axis_ex<double>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
+                                        const double*, double*, size_t, int, int*, hipStream_t);
+template hipError_t lap_axis_ex<float>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
+                                       const double*, double*, size_t, int, int*, hipStream_t);
+template hipError_t hvp_xpass<double>(int, const LapAxis&, size_t, const void*, const void*, const void*,
+                                      const double*, void*, const PwParams&, double*, size_t, int*, hipStream_t);
+template hipError_t hvp_xpass<float>(int, const LapAxis&, size_t, const void*, const void*, const void*,
+                                     const float*, void*, const PwParams&, double*, size_t, int*, hipStream_t);
 
 }  // namespace gpe

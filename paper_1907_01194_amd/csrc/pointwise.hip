@@ -1,123 +1,9 @@
-// Pointwise spin-F terms of the energy, gradient and Hessian-vector product
-// (Sec. 2 energies, Sec. 3 discrete forms).
-//
-// Per grid point the kernels hold the K = 2F+1 components in registers and
-// use the sparse structure of the spin matrices instead of dense K x K
-// products:
-//   rho  = sum |X_i|^2,  F_z = sum l_i |X_i|^2,
-//   F_+  = F_x + i F_y = sum_i cr_i conj(X_{i-1}) X_i   (raising operator,
-//          cr_i = sqrt(F(F+1) - m(m+1)) for m = l_i),
-//   (F.f Y)_i = F_z l_i Y_i + 1/2 [conj(F_+) cr_{i+1} Y_{i+1} + F_+ cr_i Y_{i-1}],
-//   A00  = X^T A X = sum_i s_i X_i X_{K-1-i},  s_i = (-1)^i / sqrt(K)   (F = 2, 3),
-//   A2m  = X^T A_m X = sum_i a_m(i) X_i X_{6-m-i},  m = -2..2            (F = 3),
-// where a_m are the anti-diagonal entries of the spin-3 matrices A_0, A_{+-1},
-// A_{+-2} exactly as printed in Sec. 2 (A_0 centre entry sqrt(2/3)/sqrt(7)).
-// Storage index i holds l_i = F - i.
-#include "common.h"
-#include "kernels.h"
+// Pointwise energy density and gradient kernels (Sec. 3 discrete energy and
+// gradient), built on the spin algebra of spin.h.  The pointwise part of the
+// Hessian-vector product is fused into the x-axis Laplacian pass (lap.hip).
+#include "spin.h"
 
 namespace gpe {
-
-template <int F> struct Spin;
-
-template <> struct Spin<1> {
-  static constexpr int K = 3;
-};
-template <> struct Spin<2> {
-  static constexpr int K = 5;
-};
-template <> struct Spin<3> {
-  static constexpr int K = 7;
-};
-
-// raising-operator coefficient cr_i (i = 1..K-1), couples storage i-1 <- i
-template <int F> __host__ __device__ constexpr double raise_c(int i) {
-  // F(F+1) - m(m+1) with m = F - i
-  return (F == 1) ? 1.4142135623730950488
-       : (F == 2) ? ((i == 1 || i == 4) ? 2.0 : 2.4494897427831780982)
-       : ((i == 1 || i == 6) ? 2.4494897427831780982
-          : (i == 2 || i == 5) ? 3.1622776601683793320 : 3.4641016151377545871);
-}
-
-// spin-3 quintet anti-diagonal coefficients, a[m+2][i], pair partner 6 - m - i
-// (values of the printed matrices A_{-2}, A_{-1}, A_0, A_1, A_2 divided by sqrt 7)
-__device__ __constant__ double kA2[5][7] = {
-    // m = -2: entries on i = 2..6: sqrt(5/6), -sqrt(5/3), sqrt(2), -sqrt(5/3), sqrt(5/6)
-    {0.0, 0.0, 0.34503277967117707, -0.48795003647426659, 0.53452248382484879,
-     -0.48795003647426659, 0.34503277967117707},
-    // m = -1: i = 1..6: 5/(2 sqrt 3), -sqrt5/2, 1/sqrt6, 1/sqrt6, -sqrt5/2, 5/(2 sqrt 3)
-    {0.0, 0.54554472558998102, -0.42257712736425829, 0.15430334996209191, 0.15430334996209191,
-     -0.42257712736425829, 0.54554472558998102},
-    // m = 0: i = 0..6: 5/(2 sqrt 3), 0, -sqrt3/2, sqrt(2/3), -sqrt3/2, 0, 5/(2 sqrt 3)
-    {0.54554472558998102, 0.0, -0.32732683535398857, 0.30860669992418382, -0.32732683535398857,
-     0.0, 0.54554472558998102},
-    // m = 1: i = 0..5
-    {0.54554472558998102, -0.42257712736425829, 0.15430334996209191, 0.15430334996209191,
-     -0.42257712736425829, 0.54554472558998102, 0.0},
-    // m = 2: i = 0..4
-    {0.34503277967117707, -0.48795003647426659, 0.53452248382484879, -0.48795003647426659,
-     0.34503277967117707, 0.0, 0.0}};
-
-template <int F> __device__ constexpr double singlet_s(int i) {
-  return ((i & 1) ? -1.0 : 1.0) / (F == 2 ? 2.2360679774997896964 : 2.6457513110645905905);
-}
-
-// Spin densities of one point.
-template <typename T, int F> struct Dens {
-  using T2 = c_t<T>;
-  T rho, fz;
-  T2 fp;        // F_+
-  T2 a00;       // singlet pair amplitude
-  T2 a2[5];     // quintet amplitudes (F = 3)
-};
-
-template <typename T, int F>
-__device__ __forceinline__ void densities(const c_t<T> (&x)[2 * F + 1], Dens<T, F>& d) {
-  using T2 = c_t<T>;
-  constexpr int K = 2 * F + 1;
-  d.rho = 0;
-  d.fz = 0;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const T a = cabs2(x[i]);
-    d.rho += a;
-    d.fz += T(F - i) * a;
-  }
-  d.fp = mk<T2>(0, 0);
-#pragma unroll
-  for (int i = 1; i < K; ++i) {
-    const T c = (T)raise_c<F>(i);
-    d.fp = cadd(d.fp, cscale(cmulc(x[i - 1], x[i]), c));
-  }
-  if constexpr (F >= 2) {
-    d.a00 = mk<T2>(0, 0);
-#pragma unroll
-    for (int i = 0; i < K; ++i) d.a00 = cadd(d.a00, cscale(cmul(x[i], x[K - 1 - i]), (T)singlet_s<F>(i)));
-  }
-  if constexpr (F == 3) {
-#pragma unroll
-    for (int mi = 0; mi < 5; ++mi) {
-      T2 s = mk<T2>(0, 0);
-#pragma unroll
-      for (int i = 0; i < 7; ++i) {
-        const int k = 8 - mi - i;
-        if (k >= 0 && k < 7) s = cadd(s, cscale(cmul(x[i], x[k]), (T)kA2[mi][i]));
-      }
-      d.a2[mi] = s;
-    }
-  }
-}
-
-// (F.f Y)_i with spin vector given by (fz, fp)
-template <typename T, int F>
-__device__ __forceinline__ c_t<T> ffy(T fz, c_t<T> fp, const c_t<T> (&y)[2 * F + 1], int i) {
-  using T2 = c_t<T>;
-  constexpr int K = 2 * F + 1;
-  T2 r = cscale(y[i], fz * T(F - i));
-  if (i + 1 < K) r = cadd(r, cscale(cmulc(fp, y[i + 1]), (T)(0.5 * raise_c<F>(i + 1))));
-  if (i >= 1) r = cadd(r, cscale(cmul(fp, y[i - 1]), (T)(0.5 * raise_c<F>(i))));
-  return r;
-}
 
 template <typename T, int F, bool GRAD>
 __global__ void __launch_bounds__(kRedThreads)
@@ -165,100 +51,13 @@ pw_grad_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ LX, cons
 #pragma unroll
           for (int mi = 0; mi < 5; ++mi) {
             const int k = 8 - mi - i;
-            if (k >= 0 && k < 7) nl = cadd(nl, cscale(cmulc(x[k], d.a2[mi]), (T)p.g[3] * (T)kA2[mi][i]));
+            if (k >= 0 && k < 7) nl = cadd(nl, cscale(cmulc(x[k], d.a2[mi]), (T)p.g[3] * (T)a2coef(mi, i)));
           }
         }
         g = cadd(g, nl);
         G[i * n + j] = g;
         acc[1 + i] += (double)cdotr(x[i], g);
       }
-    }
-  }
-  block_partials<NQ>(acc, part, nblk);
-}
-
-template <typename T, int F>
-__global__ void __launch_bounds__(kRedThreads)
-pw_hvp_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, const c_t<T>* __restrict__ LZ,
-              const T* __restrict__ V, c_t<T>* __restrict__ W,
-              double* __restrict__ part, int nblk, size_t n, PwParams p) {
-  using T2 = c_t<T>;
-  constexpr int K = 2 * F + 1;
-  constexpr int NQ = 4 * K;
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  T zcoef[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) zcoef[i] = (T)p.zc[i];
-  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
-    T2 x[K], z[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      x[i] = X[i * n + j];
-      z[i] = Z[i * n + j];
-    }
-    const T v = V[j];
-    Dens<T, F> d;
-    densities<T, F>(x, d);
-    // linearised densities
-    T drho = 0, dfz = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const T r = cdotr(z[i], x[i]);
-      drho += r;
-      dfz += T(F - i) * r;
-    }
-    drho *= T(2);
-    dfz *= T(2);
-    T2 dfp = mk<T2>(0, 0);
-#pragma unroll
-    for (int i = 1; i < K; ++i)
-      dfp = cadd(dfp, cscale(cadd(cmulc(z[i - 1], x[i]), cmulc(x[i - 1], z[i])), (T)raise_c<F>(i)));
-    T2 da00 = mk<T2>(0, 0);
-    if constexpr (F >= 2) {
-#pragma unroll
-      for (int i = 0; i < K; ++i) da00 = cadd(da00, cscale(cmul(x[i], z[K - 1 - i]), T(2) * (T)singlet_s<F>(i)));
-    }
-    T2 da2[5];
-    if constexpr (F == 3) {
-#pragma unroll
-      for (int mi = 0; mi < 5; ++mi) {
-        T2 s = mk<T2>(0, 0);
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          const int k = 8 - mi - i;
-          if (k >= 0 && k < 7) s = cadd(s, cscale(cmul(x[i], z[k]), T(2) * (T)kA2[mi][i]));
-        }
-        da2[mi] = s;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const T2 lz = LZ[i * n + j];
-      T2 w = cadd(lz, cscale(z[i], T(2) * (v + (T)p.zee[i]) + zcoef[i]));
-      T2 nl = cadd(cscale(z[i], (T)p.g[0] * d.rho), cscale(x[i], (T)p.g[0] * drho));
-      nl = cadd(nl, cscale(cadd(ffy<T, F>(d.fz, d.fp, z, i), ffy<T, F>(dfz, dfp, x, i)), (T)p.g[1]));
-      if constexpr (F >= 2) {
-        const T sc = (T)p.g[2] * (T)singlet_s<F>(i);
-        nl = cadd(nl, cscale(cadd(cmulc(z[K - 1 - i], d.a00), cmulc(x[K - 1 - i], da00)), sc));
-      }
-      if constexpr (F == 3) {
-#pragma unroll
-        for (int mi = 0; mi < 5; ++mi) {
-          const int k = 8 - mi - i;
-          if (k >= 0 && k < 7) {
-            const T sc = (T)p.g[3] * (T)kA2[mi][i];
-            nl = cadd(nl, cscale(cadd(cmulc(z[k], d.a2[mi]), cmulc(x[k], da2[mi])), sc));
-          }
-        }
-      }
-      w = cadd(w, nl);
-      W[i * n + j] = w;
-      acc[i] += (double)cdotr(x[i], w);
-      acc[K + i] += (double)cdotr(x[i], z[i]);
-      acc[2 * K + i] += (double)cdotr(z[i], w);
-      acc[3 * K + i] += (double)cabs2(z[i]);
     }
   }
   block_partials<NQ>(acc, part, nblk);
@@ -288,30 +87,8 @@ hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, do
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t pw_hvp(int F, const void* X, const void* Z, const void* LZ, const T* V, void* W,
-                  double* part, int nblk, size_t npts, const PwParams& p, hipStream_t st) {
-  using T2 = c_t<T>;
-  auto x = reinterpret_cast<const T2*>(X);
-  auto z = reinterpret_cast<const T2*>(Z);
-  auto lz = reinterpret_cast<const T2*>(LZ);
-  auto w = reinterpret_cast<T2*>(W);
-  switch (F) {
-    case 1: hipLaunchKernelGGL((pw_hvp_kernel<T, 1>), dim3(nblk), dim3(kRedThreads), 0, st, x, z, lz, V, w, part, nblk, npts, p); break;
-    case 2: hipLaunchKernelGGL((pw_hvp_kernel<T, 2>), dim3(nblk), dim3(kRedThreads), 0, st, x, z, lz, V, w, part, nblk, npts, p); break;
-    case 3: hipLaunchKernelGGL((pw_hvp_kernel<T, 3>), dim3(nblk), dim3(kRedThreads), 0, st, x, z, lz, V, w, part, nblk, npts, p); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 template hipError_t pw_grad<double>(int, const void*, const void*, const double*, void*, double*, int, size_t,
                                     const PwParams&, hipStream_t);
 template hipError_t pw_grad<float>(int, const void*, const void*, const float*, void*, double*, int, size_t,
                                    const PwParams&, hipStream_t);
-template hipError_t pw_hvp<double>(int, const void*, const void*, const void*, const double*, void*,
-                                   double*, int, size_t, const PwParams&, hipStream_t);
-template hipError_t pw_hvp<float>(int, const void*, const void*, const void*, const float*, void*,
-                                  double*, int, size_t, const PwParams&, hipStream_t);
-
 }  // namespace gpe

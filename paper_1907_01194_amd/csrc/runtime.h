@@ -27,11 +27,13 @@ struct gpe_handle {
   float* V32 = nullptr;
   gpe::LapAxis ax[3];
   void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  double* part = nullptr;      // kMaxQ * kMaxRedBlocks
+  double* part = nullptr;      // kMaxQ slots of pstride (>= kMaxRedBlocks) partial sums
+  size_t pstride = 0;
   double* res = nullptr;       // 64 doubles
   double* gram_pt = nullptr;   // ||u_i||^2 of the set point (7)
   double* gram_tmp = nullptr;  // scratch gram (7)
   double* hres = nullptr;      // pinned host mirror of res
+  unsigned int* ticket = nullptr;  // finalize completion counter (0 between launches)
   int nblk = 1;
   gpe::PwParams pw;
 
@@ -41,6 +43,8 @@ struct gpe_handle {
   void* Xp = nullptr;    // set point, c128
   void* Gp = nullptr;    // Euclidean gradient at the set point, c128
   void* Xp32 = nullptr;  // c64 copy of the set point (mixed)
+  void* LX64 = nullptr;  // L X_p (FP64 handle)
+  void* LX32 = nullptr;  // L X_p in c64 (mixed handle)
   std::vector<void*> solver_bufs;  // lazily allocated by the Newton driver
 
   // set-point state
@@ -73,7 +77,7 @@ gpe_status hip_fail(gpe_handle* h, hipError_t e, const char* where);
 
 // Kernel kinds of the timing record.
 enum KernelKind {
-  KK_LAP_X = 0, KK_LAP_Y, KK_LAP_Z, KK_PW_HVP, KK_PW_GRAD, KK_FINALIZE, KK_PROJECT, KK_NORMS,
+  KK_LAP_X = 0, KK_LAP_Y, KK_LAP_Z, KK_HVP_XPASS, KK_PW_GRAD, KK_FINALIZE, KK_PROJECT, KK_NORMS,
   KK_SCALE, KK_VECTOR, KK_COUNT
 };
 extern const char* const kKernelNames[KK_COUNT];

@@ -18,7 +18,9 @@
 //   * RGBB: first step 0.1/||grad||, BB step |<s,v>|/<v,v> clamped to
 //     [1e-20, 1e20], rho = 1e-4, delta = 0.2, varrho = 0.85;
 //   * when the energy change and the model value are both below 16 eps |E|
-//     the ratio is taken as 1; 12 rejections in a row end the run.
+//     the trial is accepted (ratio 1) iff it lowers the Riemannian gradient
+//     norm; when |<grad, xi>| <= 16 eps |E| the Armijo search is skipped and
+//     the full step is tried; 12 rejections in a row end the run.
 // In a mixed-precision handle the CG vectors, the Hessian products and the
 // model evaluations are c64 with FP64 reductions; energies, gradients,
 // retractions and the ratio are FP64.
@@ -224,12 +226,15 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
     double slope;
     GPE_TRY(dot_host(h, gR, false, xi, w32, n, &slope));
 
-    // ---- Armijo curvilinear search on the model (eq. tp1, tp2)
+    // ---- Armijo curvilinear search on the model (eq. tp1, tp2).  Near FP64
+    // resolution (|<grad, xi>| <= 16 eps |E|) model values are rounding noise:
+    // the full step is tried and the gradient norm decides below.
     RetractNorms rn;
     GPE_TRY(retract_norms(h, u, xi, w32, &rn));
+    const bool resolved = std::fabs(slope) > 16 * eps * std::fabs(E);
     double t = o->alpha0, m = 0;
     bool ok = false;
-    for (int ls = 0; ls < o->ls_max; ++ls) {
+    for (int ls = 0; resolved && ls < o->ls_max; ++ls) {
       GPE_TRY(retract_apply(h, rn, u, xi, w32, t, o->retraction, B[B_Z]));
       if (w32) GPE_HIP(h, (diff<double, double, float>(B[B_Z], u, B[B_DZ], n, s)));
       else GPE_HIP(h, (diff<double, double, double>(B[B_Z], u, B[B_DZ], n, s)));
@@ -245,12 +250,22 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
       }
       t *= o->delta;
     }
-    double ratio = -INFINITY, Ez = 0, agz = 0, bgz = 0;
+    if (!resolved) {
+      GPE_TRY(retract_apply(h, rn, u, xi, w32, t, o->retraction, B[B_Z]));
+      ok = true;
+      m = 0.0;
+    }
+    double ratio = -INFINITY, Ez = 0, agz = 0, bgz = 0, gnz = -1.0;
     if (ok) {
       GPE_TRY(eval_point(h, B[B_Z], B[B_GZ], h->gram_tmp, &Ez, &agz, &bgz));
       const double dE = Ez - E;
-      if (std::fabs(dE) <= 16 * eps * std::fabs(E) && std::fabs(m) <= 16 * eps * std::fabs(E)) ratio = 1.0;
-      else ratio = dE / m;
+      if (std::fabs(dE) <= 16 * eps * std::fabs(E) && std::fabs(m) <= 16 * eps * std::fabs(E)) {
+        // energies cannot rank u and z: the Riemannian gradient norm does
+        GPE_TRY(project_grad(h, B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz, &gnz));
+        ratio = gnz < gn ? 1.0 : -INFINITY;
+      } else {
+        ratio = dE / m;
+      }
     }
     st->outer++;
     if (o->verbose)

@@ -103,6 +103,15 @@ def spin3_3d(n=128):
                      harmonic((1.0, 1.0, 2.0)), (500, 5, -5, 2), 0.2)
 
 
+def spin3_3d_paper(n=128, case="II", M=0.5):
+    """The paper's spin-3 3D workload (Sec. 7.3, Tables 1-3-3 and 4-1): [-8,8]^3,
+    V = |x|^2/2 + 100 sum sin^2(pi x_a/2), Case I beta = (100, 1, -10, -1),
+    Case II beta = (100, 1, 10, 1)."""
+    beta = {"I": (100, 1, -10, -1), "II": (100, 1, 10, 1)}[case]
+    return make_spec("spin3-3d-%d-paper-case%s-M%g" % (n, case, M), 3, (n, n, n), (-8, -8, -8), (8, 8, 8),
+                     lattice(100.0, np.pi / 2), beta, M)
+
+
 def spin2_3d(n=96):
     """Spin-2, 3D, n^3 on [-12,12]^3, V = |x|^2/2, beta = (100, 1, -1), M = 0.3."""
     return make_spec("spin2-3d-%d" % n, 2, (n, n, n), (-12, -12, -12), (12, 12, 12),

@@ -78,3 +78,29 @@ def test_solve_spin2_2d_small(torch, prec):
     assert abs(st["E"] - st_or.E) <= tol * abs(st_or.E)
     assert st["gnorm"] <= 1e-6
     assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+
+
+def _table41_3d(case, M):
+    import os
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table4_1_spin3_3d.txt")):
+        r = line.split()
+        if r and not r[0].startswith("#") and r[0] == case and float(r[5]) == M:
+            return float(r[6])
+
+
+@pytest.mark.parametrize("case,beta", [("I", (100, 1, -10, -1)), ("II", (100, 1, 10, 1))])
+def test_solve_paper_table4_1_spin3_3d_128(torch, case, beta):
+    """Spin-3 3D ground states of Sec. 7.3 (Table 4-1, M = 0.5) on the paper's own
+    128^3 grid, lattice potential and initial data, in mixed precision."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev
+    print("solve table 4-1 3D", case, flush=True)
+    M = 0.5
+    lat = lambda *xs: 0.5 * sum(x * x for x in xs) + 100 * sum(np.sin(np.pi * x / 2) ** 2 for x in xs)
+    spec = W.make_spec("t41-3d", 3, (128, 128, 128), (-8,) * 3, (8,) * 3, lat, beta, M)
+    X0 = W.paper_initial(spec, W.paper_U(3, None, M, 0))
+    gp = Problem(spec, "mixed")
+    X, st = gp.newton_solve(dev(X0), tol=1e-6, time_limit=100.0)
+    assert st["converged"]
+    assert abs(st["E"] - _table41_3d(case, M)) <= 5e-5
+    assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
