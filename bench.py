@@ -27,6 +27,23 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
+# HBM bytes per launch of the dominant HVP kernel from the FETCH_SIZE / WRITE_SIZE
+# rocprofv3 runs recorded in profiles/hvp_spin3_128_hbm_counters.md (copy-kernel
+# calibrated); valid only while the kernel sources hash to `src_hash`.
+MEASURED_TRAFFIC = {
+    "src_hash": "44afa8319c279d46",
+    "hvp_xpass": {"mixed": 482981775, "fp64": 1127698898},
+}
+
+
+def kernel_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1907_01194_amd", "csrc")
+    for f in ("lap.hip", "spin.h", "common.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -39,7 +56,23 @@ def parse():
     ap.add_argument("--solve-time", type=float, default=45.0,
                     help="wall-clock cap per solve of the benchmark physics (s)")
     ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy kernel (reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration(log):
+    """A plain device-to-device copy kernel of known size: read 256 MiB, write
+    256 MiB, ten times.  Profiled with the same counters as the HVP kernels it
+    gives the scale factor between counter readings and bytes."""
+    import torch
+    n = 1 << 26                                    # 64 Mi floats = 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        torch.add(a, 1.0, out=b)                   # elementwise kernel: 256 MiB in, 256 MiB out
+    torch.cuda.synchronize()
+    log("copy calibration: 10 launches, %d bytes read and %d bytes written per launch" % (4 * n, 4 * n))
 
 
 def kernel_bytes(kind, K, npts, cb, rb):
@@ -106,9 +139,12 @@ def roofline(spec, prec, ms, kt):
     achieved = b / per_launch_s / 1e9
     hvp_bytes = 3 * K * npts * cb + npts * rb             # read X, Z, V; write HZ
     hvp_gbs = hvp_bytes / (ms / 1e3) / 1e9
+    traffic = None
+    if npts == 128 ** 3 and kernel_src_hash() == MEASURED_TRAFFIC["src_hash"]:
+        traffic = MEASURED_TRAFFIC.get(dom, {}).get(prec)
     return {
         "kernel": {"bound": "hbm", "name": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                    "bytes_per_launch": b, "us_per_launch": round(per_launch_s * 1e6, 2)},
         "hvp": {"bound": "hbm", "achieved": round(hvp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hvp_gbs / HBM_PEAK_GBS, 4), "compulsory_bytes": hvp_bytes,
@@ -174,6 +210,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(log)
+        return
     from paper_1907_01194_amd import workloads as W
     spec = W.spin3_3d(args.n)
     w = W.initial_state(spec, 3)
