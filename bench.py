@@ -118,12 +118,14 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log):
     ms = e0.elapsed_time(e1) / steps
     kt = gp.timing_read()
     gp.timing(False)
+    sched = gp.schedule()
+    log("%s: x-pass schedule variant %d (autotuned; us per variant %s)" % (prec, sched[0], sched[1]))
     log("%s: %.1f us per HVP (events), %.1f us (wall), kappa=%.6e" % (prec, 1e3 * ms, 1e6 * wall / steps, kappa))
     for k, (c, t) in sorted(kt.items(), key=lambda x: -x[1][1]):
         log("   %-12s %6d launches  %9.1f us avg" % (k, c, 1e3 * t / c))
     del gp
     torch.cuda.empty_cache()
-    return ms, kt
+    return ms, kt, sched
 
 
 def roofline(spec, prec, ms, kt):
@@ -220,9 +222,10 @@ def main():
     precs = args.precisions.split(",")
     res = {}
     for prec in precs:
-        ms, kt = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
+        ms, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
         res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "roofline": roofline(spec, prec, ms, kt),
-                     "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()}}
+                     "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()},
+                     "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]}}
     solves = {}
     if not args.no_solve:
         # (a) the paper's spin-3 128^3 workload (Sec. 7.3 Table 4-1 3D / Table 1-3-3,
@@ -267,7 +270,8 @@ def main():
         "hvp_roofline": res[head]["roofline"]["hvp"],
         "cpu_baseline": cpu,
         "precisions": {p: {"hvp_per_s": round(r["hvp_per_s"], 2), "ms_per_hvp": round(r["ms_per_hvp"], 4),
-                           "roofline": r["roofline"], "kernels_us": r["kernels_us"]} for p, r in res.items()},
+                           "roofline": r["roofline"], "kernels_us": r["kernels_us"],
+                           "xpass_schedule": r["xpass_schedule"]} for p, r in res.items()},
         "time_to_ground_state": solves or None,
     }
     print(json.dumps(out), flush=True)

@@ -190,6 +190,13 @@ gpe_status gpe_constraints(gpe_handle* h, const void* X, double* mass, double* m
 gpe_status gpe_newton_solve(gpe_handle* h, void* X_inout, const gpe_solve_opts* opts,
                             gpe_solve_stats* stats);
 
+/* Launch schedule chosen at creation: the fused x-pass kernel of the HVP
+ * comes in up to 3 variants (rows of the grid per workgroup: half, default,
+ * double); gpe_create times each on the handle's grid and keeps the fastest.
+ * Writes the chosen variant and up to nvariants measured times in
+ * microseconds (0 where a variant was not timed). */
+gpe_status gpe_schedule(const gpe_handle* h, int* xpass_variant, float* variant_us, int nvariants);
+
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every kernel launched by the library.  gpe_timing_enable(h, 1) clears the
  * record and starts recording; gpe_timing_read synchronises and writes, for

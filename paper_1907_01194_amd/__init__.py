@@ -8,7 +8,7 @@ the shared library; the first use of ``binding`` does, and fails loudly if the
 library has not been built.
 """
 
-__all__ = ["binding", "workloads"]
+__all__ = ["binding", "workloads", "autograd"]
 
 
 def __getattr__(name):

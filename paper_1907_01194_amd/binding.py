@@ -72,6 +72,7 @@ SIGNATURES = {
     "gpe_newton_solve": (c_int, [c_void_p, c_void_p, ctypes.POINTER(gpe_solve_opts),
                                  ctypes.POINTER(gpe_solve_stats)]),
     "gpe_project": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gpe_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_int]),
     "gpe_timing_enable": (c_int, [c_void_p, c_int]),
     "gpe_timing_read": (c_int, [c_void_p, c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(c_int),
                                 ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
@@ -231,6 +232,13 @@ class Problem:
         O = out if out is not None else self.empty()
         self._check(lib().gpe_project(self.h, self._m(X), self._m(W), self._m(O)))
         return O
+
+    def schedule(self):
+        """(chosen x-pass variant, measured microseconds per variant)."""
+        v = c_int()
+        us = (ctypes.c_float * 3)()
+        self._check(lib().gpe_schedule(self.h, ctypes.byref(v), us, 3))
+        return v.value, list(us)
 
     def timing(self, enable=True):
         self._check(lib().gpe_timing_enable(self.h, int(bool(enable))))

@@ -127,7 +127,7 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = 0;
   int nbx = 0;
   GPE_KT(h, KK_HVP_XPASS,
-         hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->st));
+         hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->xvar, h->st));
   for (int q = 0; q < 7; ++q) nb.nb[q] = nbx;
   double* coef = h->res + 32;
   if (riem)
@@ -148,6 +148,53 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   }
   GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, POST_HVP_KAPPA, h->F, h->gram_pt, h->ticket, h->st));
   return GPE_OK;
+}
+
+// Pick the fused x pass's rows-per-workgroup by timing each variant on the
+// handle's own grid (zero fields; the cost does not depend on the values).
+template <typename T>
+static gpe_status tune_xpass_t(gpe_handle* h) {
+  const int nv = xpass_variants(h->n[0]);
+  if (nv <= 1 || h->npts < (1u << 15)) return GPE_OK;
+  // three distinct zero fields for X, Z, LX (aliasing them would hide memory traffic)
+  void* A = sizeof(T) == 8 ? h->T64 : h->T32;
+  void* Bz = sizeof(T) == 8 ? h->Xp : h->Xp32;
+  void* C = sizeof(T) == 8 ? h->LX64 : h->LX32;
+  void* Wt = h->Gp;                                // scratch output (c128, large enough)
+  const T* Vw = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h->V64 : (const void*)h->V32);
+  for (void* b : {A, Bz, C}) GPE_HIP(h, hipMemsetAsync(b, 0, h->nel * sizeof(T) * 2, h->st));
+  hipEvent_t e0, e1;
+  GPE_HIP(h, hipEventCreate(&e0));
+  GPE_HIP(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestv = 1;
+  for (int v = 0; v < nv; ++v) {
+    int nb = 0;
+    GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v, h->st));
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      GPE_HIP(h, hipEventRecord(e0, h->st));
+      GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v, h->st));
+      GPE_HIP(h, hipEventRecord(e1, h->st));
+      GPE_HIP(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      GPE_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+      tmin = std::fmin(tmin, ms);
+    }
+    h->xvar_us[v] = 1e3f * tmin;
+    if (tmin < best) {
+      best = tmin;
+      bestv = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->xvar = bestv;
+  return GPE_OK;
+}
+
+gpe_status tune_xpass(gpe_handle* h) {
+  return h->prec == GPE_FP64 ? tune_xpass_t<double>(h) : tune_xpass_t<float>(h);
 }
 
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
@@ -526,6 +573,11 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
 #undef GPE_ALLOC
   e = hipStreamSynchronize(h->st);
   if (e != hipSuccess) return bail(e, "sync");
+  if (tune_xpass(h) != GPE_OK) {
+    g_create_error = h->err;
+    gpe_destroy(h);
+    return GPE_EHIP;
+  }
   *out = h;
   return GPE_OK;
 }
@@ -613,6 +665,14 @@ gpe_status gpe_project(gpe_handle* h, const void* X, const void* W, void* out) {
   const double alpha = (a22 * r1 - a12 * r2) / det, beta = (a11 * r2 - a12 * r1) / det;
   double gn;
   GPE_TRY(project_grad(h, X, W, out, alpha, beta, &gn));
+  return GPE_OK;
+}
+
+gpe_status gpe_schedule(const gpe_handle* h, int* xpass_variant, float* variant_us, int nvariants) {
+  if (!h) return fail(nullptr, GPE_EINVAL, "NULL handle");
+  if (xpass_variant) *xpass_variant = h->xvar;
+  for (int v = 0; v < nvariants && v < 3; ++v)
+    if (variant_us) variant_us[v] = h->xvar_us[v];
   return GPE_OK;
 }
 

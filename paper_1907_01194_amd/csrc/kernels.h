@@ -47,10 +47,12 @@ hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, do
 //   Y = L X), [2] sum <X_i,Z_i>, [3] sum l_i <X_i,Z_i>, [4] <Z, W - LZ>, [5] ||Z||^2,
 //   [6] <Z, L_x Z> (Parseval).
 // Returns the number of workgroups (partials per slot) in *nblk_out.
+// var: schedule variant (rows per workgroup), 0 .. xpass_variants(n)-1; 1 is the default.
 template <typename T>
 hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
-                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nblk_out,
+                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nblk_out, int var,
                      hipStream_t st);
+int xpass_variants(int n);
 
 // Axis pass with Parseval partial <Z, L_a Z> into part[slot * stride + wg] and,
 // if coef != null, the projection epilogue out -= (coef[0] + coef[1] l) X.

@@ -291,24 +291,29 @@ lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
 }
 
 // Fused x pass of the Hessian-vector product: RPB x-rows, all K components.
-template <int N, int K> struct XGeo {
+// Schedule variant VAR: 0 = half the default rows per workgroup, 1 = default
+// (about 256 threads), 2 = twice the default (if it fits 1024 threads).
+template <int N, int K, int VAR = 1> struct XGeo {
   static constexpr int TPL = Geo<N>::TPL;
   static constexpr int R0 = 256 / (K * TPL);
-  static constexpr int RPB = R0 >= 16 ? 16 : R0 >= 8 ? 8 : R0 >= 4 ? 4 : R0 >= 2 ? 2 : 1;
+  static constexpr int RD = R0 >= 16 ? 16 : R0 >= 8 ? 8 : R0 >= 4 ? 4 : R0 >= 2 ? 2 : 1;
+  static constexpr int RPB = VAR == 0 ? (RD > 1 ? RD / 2 : 1)
+                           : VAR == 1 ? RD
+                           : (2 * RD * K * TPL <= 1024 ? 2 * RD : RD);
   static constexpr int LINES = RPB * K;
   static constexpr int THREADS = ((LINES * TPL + 63) / 64) * 64;
 };
 
-template <typename T, int N, int F>
-__global__ void __launch_bounds__((XGeo<N, 2 * F + 1>::THREADS))
+template <typename T, int N, int F, int VAR>
+__global__ void __launch_bounds__((XGeo<N, 2 * F + 1, VAR>::THREADS))
 hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, const c_t<T>* __restrict__ Y,
                  const T* __restrict__ V, c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
                  size_t npts, T lamc, PwParams p, double* __restrict__ part, size_t stride) {
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
   constexpr int TPL = Geo<N>::TPL;
-  constexpr int RPB = XGeo<N, K>::RPB;
-  constexpr int LINES = XGeo<N, K>::LINES;
+  constexpr int RPB = XGeo<N, K, VAR>::RPB;
+  constexpr int LINES = XGeo<N, K, VAR>::LINES;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* tw = reinterpret_cast<T2*>(smem_raw);
   T2* lds = tw + N;
@@ -450,35 +455,51 @@ hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void*
   return hipGetLastError();
 }
 
-template <typename T, int N, int F>
+template <typename T, int N, int F, int VAR>
 static void launch_xpass(const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y, const T* V,
                          void* W, const PwParams& p, double* part, size_t stride, int* nb, hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
-  using G = XGeo<N, K>;
+  using G = XGeo<N, K, VAR>;
   const long nrows = (long)(npts / N);
   const int grid = (int)((nrows + G::RPB - 1) / G::RPB);
   const size_t lds = sizeof(T2) * (size_t)(N + G::LINES * (N + 1));
   const T2* tw = reinterpret_cast<const T2*>(sizeof(T) == 8 ? ax.tw64 : ax.tw32);
   if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hvp_xpass_kernel<T, N, F>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hvp_xpass_kernel<T, N, F, VAR>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((hvp_xpass_kernel<T, N, F>), dim3(grid), dim3(G::THREADS), lds, st,
+  hipLaunchKernelGGL((hvp_xpass_kernel<T, N, F, VAR>), dim3(grid), dim3(G::THREADS), lds, st,
                      reinterpret_cast<const T2*>(X), reinterpret_cast<const T2*>(Z),
                      reinterpret_cast<const T2*>(Y), V, reinterpret_cast<T2*>(W), tw, nrows, npts, (T)ax.lamc, p,
                      part, stride);
   *nb = grid;
 }
 
+// the line lengths that get all three schedule variants (the others use the default)
+static constexpr bool tuned_size(int n) { return n == 64 || n == 96 || n == 128 || n == 256; }
+
+template <typename T, int N, int F>
+static void launch_xpass_var(int var, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
+                             const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb,
+                             hipStream_t st) {
+  if constexpr (tuned_size(N)) {
+    if (var == 0) return launch_xpass<T, N, F, 0>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
+    if (var == 2) return launch_xpass<T, N, F, 2>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
+  }
+  launch_xpass<T, N, F, 1>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
+}
+
+int xpass_variants(int n) { return tuned_size(n) ? 3 : 1; }
+
 template <typename T>
 hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
-                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb,
+                     const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb, int var,
                      hipStream_t st) {
   switch (ax.n * 4 + F) {
-#define GPE_CASE(NN)                                                                                  \
-  case NN * 4 + 1: launch_xpass<T, NN, 1>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
-  case NN * 4 + 2: launch_xpass<T, NN, 2>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
-  case NN * 4 + 3: launch_xpass<T, NN, 3>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break;
+#define GPE_CASE(NN)                                                                                            \
+  case NN * 4 + 1: launch_xpass_var<T, NN, 1>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
+  case NN * 4 + 2: launch_xpass_var<T, NN, 2>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
+  case NN * 4 + 3: launch_xpass_var<T, NN, 3>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -492,7 +513,7 @@ size_t lap_max_blocks(const LapAxis& ax, int K) {
 #define GPE_CASE(NN)                                                                       \
   case NN:                                                                                 \
     lpb = Geo<NN>::LPB;                                                                    \
-    rpb = K == 3 ? XGeo<NN, 3>::RPB : K == 5 ? XGeo<NN, 5>::RPB : XGeo<NN, 7>::RPB;       \
+    rpb = 1; /* the smallest rows-per-workgroup of any schedule variant */               \
     break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
@@ -517,8 +538,9 @@ template hipError_t lap_axis_ex<double>(const LapAxis&, const void*, const void*
 template hipError_t lap_axis_ex<float>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
                                        const double*, double*, size_t, int, int*, hipStream_t);
 template hipError_t hvp_xpass<double>(int, const LapAxis&, size_t, const void*, const void*, const void*,
-                                      const double*, void*, const PwParams&, double*, size_t, int*, hipStream_t);
+                                      const double*, void*, const PwParams&, double*, size_t, int*, int,
+                                      hipStream_t);
 template hipError_t hvp_xpass<float>(int, const LapAxis&, size_t, const void*, const void*, const void*,
-                                     const float*, void*, const PwParams&, double*, size_t, int*, hipStream_t);
+                                     const float*, void*, const PwParams&, double*, size_t, int*, int, hipStream_t);
 
 }  // namespace gpe

@@ -35,6 +35,8 @@ struct gpe_handle {
   double* hres = nullptr;      // pinned host mirror of res
   unsigned int* ticket = nullptr;  // finalize completion counter (0 between launches)
   int nblk = 1;
+  int xvar = 1;                // schedule variant of the fused x pass (autotuned)
+  float xvar_us[3] = {0, 0, 0};  // measured microseconds per variant (0: not measured)
   gpe::PwParams pw;
 
   // owned fields
@@ -149,5 +151,6 @@ gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* si
 gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out);
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
+gpe_status tune_xpass(gpe_handle* h);
 
 }  // namespace gpe
