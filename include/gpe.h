@@ -94,8 +94,12 @@ typedef struct gpe_solve_opts {
   int cg_maxit;          /* truncated-CG iterations per subproblem (500) */
   double cg_T, cg_theta; /* CG stop ||r|| <= min(T, ||g||^theta) ||g|| (0.1, 1) */
   int max_reject_streak; /* consecutive ARNT rejections that end the run (12) */
+  double sigma_hat_min;  /* lower bound of sigma_hat (1e-8) */
   int verbose;           /* 1: one line per outer iteration on stderr */
   double time_limit;     /* seconds of wall clock after which the run stops unconverged (0: none) */
+  int mg_levels;         /* cascadic multigrid (Algorithm 1, outer loop): number of coarser meshes,
+                            each halving every axis of the same box (0: one mesh) */
+  double mg_coarse_tol;  /* ||grad|| tolerance on the coarse meshes (Sec. 7.1: 1e-5) */
 } gpe_solve_opts;
 
 typedef struct gpe_solve_stats {
@@ -113,6 +117,8 @@ typedef struct gpe_solve_stats {
   double t_arnt;
   double mass_err;       /* |mass - 1| of the result */
   double mag_err;        /* |magnetization - M| of the result */
+  int mg_levels;         /* coarse meshes actually used */
+  double t_coarse;       /* seconds spent on the coarse meshes (included in t_total) */
 } gpe_solve_stats;
 
 /* Fill *opts with the defaults listed in gpe_solve_opts.  Never fails. */
@@ -174,6 +180,14 @@ gpe_status gpe_retract(gpe_handle* h, const void* X, const void* Xi, double t, i
  * the measured Gram matrix of u and Gamma u): out = W - alpha X - beta Gamma X.
  * X, W, out: device c128 fields; out may alias W.  Synchronises. */
 gpe_status gpe_project(gpe_handle* h, const void* X, const void* W, void* out);
+
+/* Prolongation for the cascadic multigrid (Algorithm 1): Xf = Fourier
+ * interpolant of Xc on the mesh of `fine`, which must have twice the points
+ * of `coarse` on every axis of the same box (coarse node j = fine node 2j);
+ * the sqrt(h) scaling is carried over (Xf = 2^{-d/2} interp(Xc)).  Xc, Xf:
+ * device c128 fields of the two handles.  Uses the fine handle's scratch, so
+ * a prior gpe_set_point on `fine` must be repeated.  Synchronises. */
+gpe_status gpe_prolong(const gpe_handle* coarse, const void* Xc, gpe_handle* fine, void* Xf);
 
 /* Mass and magnetization of a c128 field (FP64 reductions); synchronises. */
 gpe_status gpe_constraints(gpe_handle* h, const void* X, double* mass, double* mag);

@@ -31,7 +31,9 @@ trial is then accepted (ratio 1) if and only if it lowers the Riemannian
 gradient norm; and when the predicted decrease |<grad, xi>| is itself below
 16 eps |E| the Armijo search (whose model values are then rounding noise) is
 skipped and the full step alpha0 xi is tried.  Twelve rejections in a row end
-the run unconverged.
+the run unconverged.  sigma_hat never drops below 1e-8 (repeated very
+successful steps would otherwise drive it to underflow, after which the
+increases on rejection can no longer restore any regularisation).
 """
 
 from dataclasses import dataclass, field
@@ -68,6 +70,7 @@ class SolveOpts:
     cg_maxit: int = 500
     cg_T: float = 0.1
     cg_theta: float = 1.0
+    sigma_hat_min: float = 1e-8
     max_reject_streak: int = 12
 
 
@@ -216,7 +219,7 @@ def arnt(prob, u, opts, stats):
             u, E = z, Ez
             gR, G, ag, bg = rgrad(prob, u, Gz)
             gn = _norm(gR)
-            shat *= opts.gamma0 if ratio >= opts.eta2 else opts.gamma1
+            shat = max(shat * (opts.gamma0 if ratio >= opts.eta2 else opts.gamma1), opts.sigma_hat_min)
             streak = 0
         else:
             stats.rejected += 1

@@ -43,14 +43,16 @@ class gpe_solve_opts(ctypes.Structure):
                 ("gamma2", c_double), ("sigma_hat0", c_double),
                 ("rho", c_double), ("delta", c_double), ("alpha0", c_double),
                 ("ls_max", c_int), ("cg_maxit", c_int), ("cg_T", c_double), ("cg_theta", c_double),
-                ("max_reject_streak", c_int), ("verbose", c_int), ("time_limit", c_double)]
+                ("max_reject_streak", c_int), ("sigma_hat_min", c_double), ("verbose", c_int), ("time_limit", c_double),
+                ("mg_levels", c_int), ("mg_coarse_tol", c_double)]
 
 
 class gpe_solve_stats(ctypes.Structure):
     _fields_ = [("E", c_double), ("gnorm", c_double), ("converged", c_int), ("rgbb_iters", c_int),
                 ("outer", c_int), ("cg_total", c_int), ("hvp_calls", c_int), ("ls_trials", c_int),
                 ("rejected", c_int), ("t_total", c_double), ("t_rgbb", c_double),
-                ("t_arnt", c_double), ("mass_err", c_double), ("mag_err", c_double)]
+                ("t_arnt", c_double), ("mass_err", c_double), ("mag_err", c_double),
+                ("mg_levels", c_int), ("t_coarse", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,6 +74,7 @@ SIGNATURES = {
     "gpe_newton_solve": (c_int, [c_void_p, c_void_p, ctypes.POINTER(gpe_solve_opts),
                                  ctypes.POINTER(gpe_solve_stats)]),
     "gpe_project": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gpe_prolong": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "gpe_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_int]),
     "gpe_timing_enable": (c_int, [c_void_p, c_int]),
     "gpe_timing_read": (c_int, [c_void_p, c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(c_int),
@@ -232,6 +235,12 @@ class Problem:
         O = out if out is not None else self.empty()
         self._check(lib().gpe_project(self.h, self._m(X), self._m(W), self._m(O)))
         return O
+
+    def prolong(self, Xc, fine, out=None):
+        """Fourier prolongation of Xc (this handle's mesh) onto ``fine`` (2n per axis)."""
+        Xf = out if out is not None else fine.empty()
+        self._check(lib().gpe_prolong(self.h, self._m(Xc), fine.h, fine._m(Xf)))
+        return Xf
 
     def schedule(self):
         """(chosen x-pass variant, measured microseconds per variant)."""

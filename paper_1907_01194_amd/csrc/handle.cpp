@@ -361,6 +361,59 @@ gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool 
   return GPE_OK;
 }
 
+// Interpolation matrix of the Fourier interpolant from n nodes to the 2n nodes
+// of the refined axis: P[j'][k] = (1/n) sum_{p=-n/2}^{n/2} c_p e^{i 2 pi p (j'/(2n) - k/n)},
+// c_{+-n/2} = 1/2 (real: the sum pairs p and -p).
+static std::vector<double> interp_matrix(int n) {
+  std::vector<double> P((size_t)2 * n * n);
+  for (int jp = 0; jp < 2 * n; ++jp)
+    for (int k = 0; k < n; ++k) {
+      const double th = M_PI * (double)(jp - 2 * k) / (double)n;
+      double s = 1.0 + std::cos(0.5 * n * th);
+      for (int p = 1; p < n / 2; ++p) s += 2.0 * std::cos(p * th);
+      P[(size_t)jp * n + k] = s / n;
+    }
+  return P;
+}
+
+gpe_status prolong(const gpe_handle* c, const void* Xc, gpe_handle* f, void* Xf) {
+  if (c->F != f->F || c->dim != f->dim) return fail(f, GPE_EINVAL, "prolong: problems differ");
+  for (int a = 0; a < c->dim; ++a)
+    if (f->n[a] != 2 * c->n[a]) return fail(f, GPE_EINVAL, "prolong: fine grid must have 2n points per axis");
+  // ping-pong through the fine handle's scratch (T64, Gp); the set point is lost
+  f->has_point = false;
+  const void* src = Xc;
+  size_t sizes[3] = {(size_t)c->n[0], (size_t)c->n[1], (size_t)c->n[2]};
+  std::vector<double*> mats;
+  gpe_status rs = GPE_OK;
+  for (int a = 0; a < c->dim && rs == GPE_OK; ++a) {
+    const int n = c->n[a];
+    std::vector<double> P = interp_matrix(n);
+    double* dP = nullptr;
+    rs = alloc_field(f, (void**)&dP, P.size() * sizeof(double));
+    if (rs != GPE_OK) break;
+    mats.push_back(dP);
+    hipError_t e = hipMemcpyAsync(dP, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, f->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->st);   // P is a stack vector
+    if (e != hipSuccess) { rs = hip_fail(f, e, "copy interpolation matrix"); break; }
+    size_t inner = 1, outer = (size_t)c->K;
+    for (int b = 0; b < a; ++b) inner *= sizes[b];
+    for (int b = a + 1; b < c->dim; ++b) outer *= sizes[b];
+    const bool last = a == c->dim - 1;
+    void* dst = last ? Xf : (a == 0 ? f->T64 : f->Gp);
+    const double scale = last ? std::pow(2.0, -0.5 * c->dim) : 1.0;
+    e = prolong_axis(src, dst, dP, n, inner, outer, scale, f->st);
+    if (e != hipSuccess) { rs = hip_fail(f, e, "prolong_axis"); break; }
+    sizes[a] = 2 * (size_t)n;
+    src = dst;
+  }
+  hipError_t e = hipStreamSynchronize(f->st);
+  for (double* m : mats) (void)hipFree(m);
+  if (rs != GPE_OK) return rs;
+  if (e != hipSuccess) return hip_fail(f, e, "prolong sync");
+  return GPE_OK;
+}
+
 }  // namespace gpe
 
 using namespace gpe;
@@ -402,8 +455,11 @@ void gpe_solve_opts_default(gpe_solve_opts* o) {
   o->cg_T = 0.1;
   o->cg_theta = 1.0;
   o->max_reject_streak = 12;
+  o->sigma_hat_min = 1e-8;
   o->verbose = 0;
   o->time_limit = 0.0;
+  o->mg_levels = 0;
+  o->mg_coarse_tol = 1e-5;
 }
 
 const char* gpe_last_error(const gpe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
@@ -446,6 +502,7 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     if (!(pr->hi[a] > pr->lo[a])) return fail(nullptr, GPE_EINVAL, "empty box");
   }
   gpe_handle* h = new gpe_handle();
+  h->prob = *pr;
   h->F = pr->F;
   h->K = 2 * pr->F + 1;
   h->dim = pr->dim;
@@ -467,6 +524,7 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     h->h *= (pr->hi[a] - pr->lo[a]) / pr->n[a];
   }
   h->nel = h->npts * h->K;
+  h->Vhost.assign(V_host, V_host + h->npts);
   (void)hipGetDevice(&h->device);
 
   // pointwise constants
@@ -666,6 +724,11 @@ gpe_status gpe_project(gpe_handle* h, const void* X, const void* W, void* out) {
   double gn;
   GPE_TRY(project_grad(h, X, W, out, alpha, beta, &gn));
   return GPE_OK;
+}
+
+gpe_status gpe_prolong(const gpe_handle* coarse, const void* Xc, gpe_handle* fine, void* Xf) {
+  if (!coarse || !fine || !Xc || !Xf) return fail(fine, GPE_EINVAL, "NULL argument");
+  return gpe::prolong(coarse, Xc, fine, Xf);
 }
 
 gpe_status gpe_schedule(const gpe_handle* h, int* xpass_variant, float* variant_us, int nvariants) {

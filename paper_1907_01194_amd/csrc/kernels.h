@@ -124,4 +124,13 @@ hipError_t to_c128(const void* src, void* dst, size_t n, hipStream_t st);
 template <typename TA, typename TB, typename TO>
 hipError_t diff(const void* a, const void* b, void* out, size_t n, hipStream_t st);
 
+// Multigrid transfer (c128 fields).  prolong_axis: out[o][j'][i] = scale *
+// sum_k P[j' n + k] in[o][k][i] with j' < 2n (P real, on the device).
+// restrict_inject: coarse[c][z][y][x] = scale * fine[c][2z][2y][2x] (nc = coarse
+// sizes, x first).
+hipError_t prolong_axis(const void* in, void* out, const double* P, int n, size_t inner, size_t outer, double scale,
+                        hipStream_t st);
+hipError_t restrict_inject(const void* fine, void* coarse, int K, int dim, const int* nc, double scale,
+                           hipStream_t st);
+
 }  // namespace gpe

@@ -19,6 +19,8 @@ struct gpe_handle {
   size_t nel = 0;    // K * npts complex elements per field
   double h = 0;      // prod_a h_a
   int prec = GPE_FP64;
+  gpe_problem prob;                 // as given at creation
+  std::vector<double> Vhost;        // potential on the grid (host copy, for coarse meshes)
   hipStream_t st = nullptr;
   int device = 0;
 
@@ -152,5 +154,7 @@ gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool 
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
 gpe_status tune_xpass(gpe_handle* h);
+// Fourier prolongation of a c128 field from `coarse` to `fine` (2n per axis).
+gpe_status prolong(const gpe_handle* coarse, const void* Xc, gpe_handle* fine, void* Xf);
 
 }  // namespace gpe

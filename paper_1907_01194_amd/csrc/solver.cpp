@@ -20,7 +20,10 @@
 //   * when the energy change and the model value are both below 16 eps |E|
 //     the trial is accepted (ratio 1) iff it lowers the Riemannian gradient
 //     norm; when |<grad, xi>| <= 16 eps |E| the Armijo search is skipped and
-//     the full step is tried; 12 rejections in a row end the run.
+//     the full step is tried; 12 rejections in a row end the run;
+//   * sigma_hat is kept >= sigma_hat_min (1e-8): a run of very successful
+//     steps would otherwise drive it to underflow, and the x10 increases on
+//     rejection could then never restore any regularisation.
 // In a mixed-precision handle the CG vectors, the Hessian products and the
 // model evaluations are c64 with FP64 reductions; energies, gradients,
 // retractions and the ratio are FP64.
@@ -31,6 +34,8 @@
 #include <cstdio>
 #include <cstring>
 #include <utility>
+#include <vector>
+#include <string>
 
 #include "runtime.h"
 
@@ -75,7 +80,7 @@ gpe_status ensure_bufs(gpe_handle* h) {
 
 }  // namespace
 
-gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
+static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
   Clock clk;
   GPE_TRY(ensure_bufs(h));
   auto& B = h->solver_bufs;
@@ -285,7 +290,7 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
       h->alpha_g = ag;
       h->beta_g = bg;
       GPE_TRY(adopt_point(h));
-      shat *= ratio >= o->eta2 ? o->gamma0 : o->gamma1;
+      shat = std::fmax(shat * (ratio >= o->eta2 ? o->gamma0 : o->gamma1), o->sigma_hat_min);
       streak = 0;
     } else {
       st->rejected++;
@@ -307,6 +312,95 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
   st->t_total = clk.sec();
   if (!converged) return fail(h, GPE_ENOTCONV, "tolerance not reached");
   return GPE_OK;
+}
+
+// Cascadic multigrid (Algorithm 1, outer loop): solve on the coarsest of
+// mg_levels nested meshes (every axis halved per level, same box, V and the
+// initial state injected), then prolong each solution as the next finer
+// mesh's initial guess (Fourier interpolation); coarse meshes stop at
+// mg_coarse_tol (Sec. 7.1: 1e-5), the finest at tol.
+gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
+  int L = o->mg_levels;
+  // the coarsest admissible level: every used axis stays even, supported, >= 8
+  for (int l = 1; l <= L; ++l)
+    for (int a = 0; a < h->dim; ++a) {
+      const int m = h->n[a] >> l;
+      if ((h->n[a] % (1 << l)) || m < 8 || m % 2 || !lap_size_supported(m)) {
+        L = l - 1;
+        break;
+      }
+    }
+  if (L <= 0) {
+    gpe_status r = newton_solve_one(h, Xio, o, st);
+    st->mg_levels = 0;
+    return r;
+  }
+  Clock clk;
+  std::vector<gpe_handle*> hs(L + 1, nullptr);
+  std::vector<void*> xs(L + 1, nullptr);
+  hs[0] = h;
+  xs[0] = Xio;
+  gpe_status rs = GPE_OK;
+  for (int l = 1; l <= L && rs == GPE_OK; ++l) {
+    const gpe_handle* f = hs[l - 1];
+    gpe_problem pc = f->prob;
+    std::vector<double> Vc;
+    int nc[3] = {1, 1, 1};
+    for (int a = 0; a < f->dim; ++a) {
+      pc.n[a] = f->n[a] / 2;
+      nc[a] = pc.n[a];
+    }
+    Vc.resize((size_t)nc[0] * nc[1] * nc[2]);
+    const int sy = f->dim > 1 ? 2 : 1, sz = f->dim > 2 ? 2 : 1;
+    for (int z = 0; z < nc[2]; ++z)
+      for (int y = 0; y < nc[1]; ++y)
+        for (int x = 0; x < nc[0]; ++x)
+          Vc[((size_t)z * nc[1] + y) * nc[0] + x] =
+              f->Vhost[((size_t)(z * sz) * f->n[1] + (size_t)(y * sy)) * f->n[0] + 2 * x];
+    rs = gpe_create(&pc, Vc.data(), h->prec, h->st, &hs[l]);
+    if (rs != GPE_OK) {
+      fail(h, rs, std::string("multigrid: coarse handle: ") + gpe_last_error(nullptr));
+      hs[l] = nullptr;
+      break;
+    }
+    rs = alloc_field(h, &xs[l], hs[l]->nel * 16);
+    if (rs != GPE_OK) break;
+    hipError_t e = restrict_inject(xs[l - 1], xs[l], h->K, h->dim, nc, std::pow(2.0, 0.5 * h->dim), h->st);
+    if (e != hipSuccess) rs = hip_fail(h, e, "restrict_inject");
+  }
+  double t_coarse = 0.0;
+  for (int l = L; l >= 1 && rs == GPE_OK; --l) {
+    gpe_solve_opts oc = *o;
+    oc.tol = o->mg_coarse_tol;
+    oc.mg_levels = 0;
+    if (o->time_limit > 0) oc.time_limit = std::fmax(o->time_limit - clk.sec(), 1e-3);
+    gpe_solve_stats sc;
+    std::memset(&sc, 0, sizeof(sc));
+    gpe_status r = newton_solve_one(hs[l], xs[l], &oc, &sc);
+    if (r != GPE_OK && r != GPE_ENOTCONV) {
+      rs = fail(h, r, std::string("multigrid: coarse solve: ") + hs[l]->err);
+      break;
+    }
+    if (o->verbose)
+      std::fprintf(stderr, "mg level %d (%dx%dx%d): E=%.12f |g|=%.3e outer=%d cg=%d %.2fs\n", l, hs[l]->n[0],
+                   hs[l]->n[1], hs[l]->n[2], sc.E, sc.gnorm, sc.outer, sc.cg_total, sc.t_total);
+    rs = prolong(hs[l], xs[l], hs[l - 1], xs[l - 1]);
+    if (rs != GPE_OK && hs[l - 1] != h) h->err = hs[l - 1]->err;
+  }
+  t_coarse = clk.sec();
+  for (int l = 1; l <= L; ++l) {
+    if (xs[l]) (void)hipFree(xs[l]);
+    if (hs[l]) gpe_destroy(hs[l]);
+  }
+  if (rs != GPE_OK) return rs;
+  gpe_solve_opts of = *o;
+  of.mg_levels = 0;
+  if (o->time_limit > 0) of.time_limit = std::fmax(o->time_limit - clk.sec(), 1e-3);
+  gpe_status r = newton_solve_one(h, Xio, &of, st);   // counters: finest mesh only
+  st->mg_levels = L;
+  st->t_coarse = t_coarse;
+  st->t_total += t_coarse;
+  return r;
 }
 
 }  // namespace gpe
