@@ -11,8 +11,9 @@ float64 with NumPy and scipy.fft.
 
 Each function cites the passage of the paper it follows.  Everything here is
 the plain definition: the matrix forms of Sec. 3 (with dense spin matrices),
-the projection and Hessian of Lemmas 4.1 and 4.2, the retractions of
-Lemmas 5.1, 5.3 and 5.5 and Algorithm 1.  No blocking, fusion or reordering
+the projection and Hessian lemmas of Sec. 4, the projective, orthogonal
+and closed-form retractions of Sec. 6, Algorithm 1 of Sec. 5 and its mesh
+transfer (multigrid.py).  No blocking, fusion or reordering
 beyond what those definitions state.
 
 Parity status of each part is listed in ``PINS``; a part without a pin to
@@ -32,8 +33,9 @@ PINS = {
     "hvp": "finite differences; phase/spin-rotation/homogeneity identities; symmetry",
     "projection/rgrad/rhess": "tangency, idempotence, Lemma 4.1 closed form",
     "retractions": "constraints exact; R(0)=u; second order; R1 = brute-force nearest point; "
-                   "Lemma 5.2 cases 1-3",
+                   "spin-1 closed-form cases 1-3 (Sec. 6.1)",
     "solver": "paper Table 3-1 / Table 4-1 printed ground-state energies (1D)",
+    "multigrid transfer": "coarse nodes kept; exact on trigonometric polynomials; mass preserved",
 }
 
 __all__ = [
