@@ -229,6 +229,59 @@ const char* gpe_last_error(const gpe_handle* h);
 /* Library version string. */
 const char* gpe_version(void);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent problems (one spin F and dimension; grids, boxes,
+ * potentials, interaction strengths and magnetizations may all differ)
+ * solved together.  The driver of Algorithm 1 (Sec. 5) runs for every
+ * problem in lock step: at each of its steps the device work of all problems
+ * that are at the same step is one launch per kernel stage (the fused HVP x
+ * pass, the axis passes, the finalize, the CG updates, the energy and
+ * gradient, the retraction), and the scalars of all problems come back in one
+ * copy with one synchronisation.  Each problem's iteration is exactly the
+ * one gpe_newton_solve makes (the same readings, tolerances and counters).
+ * Every grid length of a batch must be a power of two from 16 to 512.
+ */
+typedef struct gpe_batch gpe_batch;
+
+/* Create a batch of count problems (count >= 1); V_host[i] is problem i's
+ * potential (host, n_i reals).  Every problem gets its own handle (see
+ * gpe_batch_handle), all on `stream`.  The schedule of the batched fused x
+ * pass (rows per workgroup) is autotuned here on the batch's own grids.
+ * Errors: GPE_EINVAL (mixed F or dim, unsupported n, anything gpe_create
+ * rejects), GPE_ENOMEM, GPE_EHIP; message in gpe_batch_last_error(NULL). */
+gpe_status gpe_batch_create(const gpe_problem* probs, const double* const* V_host, int count, int precision,
+                            void* stream, gpe_batch** out);
+gpe_status gpe_batch_destroy(gpe_batch* b);
+gpe_status gpe_batch_size(const gpe_batch* b, int* count);
+
+/* Handle of problem i (owned by the batch: never gpe_destroy it).  Every
+ * single-problem call works on it (energy, grad, set_point, retract, ...). */
+gpe_status gpe_batch_handle(gpe_batch* b, int i, gpe_handle** h);
+
+/* HVPs of every problem at its set point (gpe_set_point on its handle
+ * first) in one batched pass: HZ[i] = Hess(Z[i]) as gpe_hvp with sigma[i]
+ * (NULL: 0); Z, HZ in the work precision.  kappa (count values, or NULL)
+ * receives <Z_i, HZ_i>.  Synchronises. */
+gpe_status gpe_batch_hvp(gpe_batch* b, const void* const* Z, void* const* HZ, int riemannian, const double* sigma,
+                         double* kappa);
+
+/* gpe_newton_solve for every problem (X_inout[i] c128, stats: count records
+ * or NULL) in lock step.  opts->mg_levels must be 0.  Returns GPE_OK when
+ * every problem converged, GPE_ENOTCONV when some did not (their stats say
+ * which), else the first problem's error.  t_total, t_rgbb and t_arnt of a
+ * problem are wall-clock times of the whole batch's run up to that
+ * problem's end of the phase. */
+gpe_status gpe_batch_newton_solve(gpe_batch* b, void* const* X_inout, const gpe_solve_opts* opts,
+                                  gpe_solve_stats* stats);
+
+/* Chosen schedule variant of the batched x pass and the measured
+ * microseconds per variant (0 if not timed; a batch of one is not timed). */
+gpe_status gpe_batch_schedule(const gpe_batch* b, int* xpass_variant, float* variant_us, int nvariants);
+
+/* Message of the last failure on the batch; for NULL, of the last failed
+ * gpe_batch_create. */
+const char* gpe_batch_last_error(const gpe_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,10 @@ and the model value are below 16 eps |E| neither can rank the two points: the
 trial is then accepted (ratio 1) if and only if it lowers the Riemannian
 gradient norm; and when the predicted decrease |<grad, xi>| is itself below
 16 eps |E| the Armijo search (whose model values are then rounding noise) is
-skipped and the full step alpha0 xi is tried.  Twelve rejections in a row end
+skipped and the full step alpha0 xi is tried; that trial has no model value,
+so unless its energy change is also below 16 eps |E| (the gradient-norm rule
+above) it is accepted if and only if the energy decreases.  Twelve rejections
+in a row end
 the run unconverged.  sigma_hat never drops below 1e-8 (repeated very
 successful steps would otherwise drive it to underflow, after which the
 increases on rejection can no longer restore any regularisation).
@@ -212,6 +215,9 @@ def arnt(prob, u, opts, stats):
             if abs(dE) <= 16 * eps * abs(E) and abs(m) <= 16 * eps * abs(E):
                 gz = rgrad(prob, z, Gz)[0]
                 ratio = 1.0 if np.sqrt(inner(gz, gz)) < gn else -np.inf
+            elif not resolved:
+                # the model value was not evaluated (m = 0): the energy alone decides
+                ratio = 1.0 if dE < 0 else -np.inf
             else:
                 ratio = dE / m
         stats.outer += 1

@@ -81,6 +81,17 @@ SIGNATURES = {
                                 ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
     "gpe_last_error": (ctypes.c_char_p, [c_void_p]),
     "gpe_version": (ctypes.c_char_p, []),
+    "gpe_batch_create": (c_int, [ctypes.POINTER(gpe_problem), ctypes.POINTER(c_void_p), c_int, c_int, c_void_p,
+                                 ctypes.POINTER(c_void_p)]),
+    "gpe_batch_destroy": (c_int, [c_void_p]),
+    "gpe_batch_size": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "gpe_batch_handle": (c_int, [c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "gpe_batch_hvp": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int,
+                              ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    "gpe_batch_newton_solve": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(gpe_solve_opts),
+                                       ctypes.POINTER(gpe_solve_stats)]),
+    "gpe_batch_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_int]),
+    "gpe_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 
 _lib = None
@@ -131,6 +142,29 @@ def _ptr(t, dtype, shape):
     return c_void_p(t.data_ptr())
 
 
+def problem_struct(spec):
+    """gpe_problem of a spec (F, n with x first, lo, hi, beta, M, p, q)."""
+    pr = gpe_problem()
+    pr.F = int(spec.F)
+    pr.dim = len(spec.n)
+    for a in range(3):
+        pr.n[a] = int(spec.n[a]) if a < pr.dim else 1
+        pr.lo[a] = float(spec.lo[a]) if a < pr.dim else 0.0
+        pr.hi[a] = float(spec.hi[a]) if a < pr.dim else 1.0
+    beta = list(spec.beta) + [0.0] * (4 - len(spec.beta))
+    for k in range(4):
+        pr.beta[k] = float(beta[k])
+    pr.p, pr.q, pr.M = float(spec.p), float(spec.q), float(spec.M)
+    return pr
+
+
+def potential(spec, grid_shape):
+    V = np.ascontiguousarray(spec.V, dtype=np.float64)
+    if V.shape != tuple(grid_shape):
+        raise ValueError("potential has shape %s, grid is %s" % (V.shape, tuple(grid_shape)))
+    return V
+
+
 class Problem:
     """One gpe handle.
 
@@ -139,7 +173,7 @@ class Problem:
     All calls are ordered on torch's current stream of ``device``.
     """
 
-    def __init__(self, spec, precision="fp64", device=0):
+    def __init__(self, spec, precision="fp64", device=0, _handle=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -150,21 +184,13 @@ class Problem:
         self.shape = (self.K,) + tuple(reversed(tuple(spec.n)))
         self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         self.work_dtype = torch.complex128 if self.precision == FP64 else torch.complex64
-        pr = gpe_problem()
-        pr.F = self.F
-        pr.dim = len(spec.n)
-        for a in range(3):
-            pr.n[a] = int(spec.n[a]) if a < pr.dim else 1
-            pr.lo[a] = float(spec.lo[a]) if a < pr.dim else 0.0
-            pr.hi[a] = float(spec.hi[a]) if a < pr.dim else 1.0
-        beta = list(spec.beta) + [0.0] * (4 - len(spec.beta))
-        for k in range(4):
-            pr.beta[k] = float(beta[k])
-        pr.p, pr.q, pr.M = float(spec.p), float(spec.q), float(spec.M)
-        V = np.ascontiguousarray(spec.V, dtype=np.float64)
-        if V.shape != self.shape[1:]:
-            raise ValueError("potential has shape %s, grid is %s" % (V.shape, self.shape[1:]))
         self.stream = torch.cuda.current_stream(self.device)
+        self._owned = _handle is None
+        if _handle is not None:        # a batch's handle: the batch owns it
+            self.h = _handle
+            return
+        pr = problem_struct(spec)
+        V = potential(spec, self.shape[1:])
         h = c_void_p()
         st = lib().gpe_create(ctypes.byref(pr), V.ctypes.data_as(c_void_p), self.precision,
                               c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -189,7 +215,8 @@ class Problem:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().gpe_destroy(self.h)
+            if self._owned:
+                lib().gpe_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -274,3 +301,82 @@ class Problem:
         if st != 0 and (check or st != 5):
             self._check(st)
         return X, s.as_dict()
+
+
+class Batch:
+    """A gpe_batch: problems of one spin F and dimension (any grids, boxes,
+    potentials and parameters) whose HVPs and Newton solves run in lock step,
+    one launch per kernel stage for all of them.  ``problems[i]`` is a
+    Problem view of problem i's handle (owned by the batch)."""
+
+    def __init__(self, specs, precision="mixed", device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        m = len(specs)
+        probs = (gpe_problem * m)(*[problem_struct(sp) for sp in specs])
+        shapes = [tuple(reversed(tuple(sp.n))) for sp in specs]
+        self._V = [potential(sp, sh) for sp, sh in zip(specs, shapes)]
+        Vp = (c_void_p * m)(*[V.ctypes.data for V in self._V])
+        b = c_void_p()
+        st = lib().gpe_batch_create(probs, Vp, m, {"fp64": FP64, "mixed": MIXED}[precision],
+                                    c_void_p(self.stream.cuda_stream), ctypes.byref(b))
+        if st != 0:
+            raise GpeError(st, lib().gpe_batch_last_error(None).decode())
+        self.b = b
+        self.problems = []
+        for i, sp in enumerate(specs):
+            h = c_void_p()
+            self._check(lib().gpe_batch_handle(self.b, i, ctypes.byref(h)))
+            self.problems.append(Problem(sp, precision, device, _handle=h))
+
+    def __len__(self):
+        return len(self.problems)
+
+    def _check(self, st):
+        if st != 0:
+            raise GpeError(st, lib().gpe_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            for p in self.problems:
+                p.h = None
+            lib().gpe_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hvp(self, Zs, riemannian=False, sigma=None, outs=None):
+        """HZ_i = Hess(Z_i) for every problem at its set point; returns (HZs, kappas)."""
+        m = len(self.problems)
+        outs = outs if outs is not None else [p.empty(work=True) for p in self.problems]
+        zp = (c_void_p * m)(*[p._w(Z).value for p, Z in zip(self.problems, Zs)])
+        hp = (c_void_p * m)(*[p._w(H).value for p, H in zip(self.problems, outs)])
+        sg = (c_double * m)(*([0.0] * m if sigma is None else [float(x) for x in sigma]))
+        kap = (c_double * m)()
+        self._check(lib().gpe_batch_hvp(self.b, zp, hp, int(bool(riemannian)), sg, kap))
+        return outs, list(kap)
+
+    def newton_solve(self, Xs, check=True, **opts):
+        """Lock-step gpe_newton_solve of every problem; returns (Xs, [stats dicts])."""
+        m = len(self.problems)
+        o = default_opts(**opts)
+        xp = (c_void_p * m)(*[p._m(X).value for p, X in zip(self.problems, Xs)])
+        stats = (gpe_solve_stats * m)()
+        st = lib().gpe_batch_newton_solve(self.b, xp, ctypes.byref(o), stats)
+        if st != 0 and (check or st != 5):
+            self._check(st)
+        return Xs, [s.as_dict() for s in stats]
+
+    def schedule(self):
+        """(chosen batched x-pass variant, measured microseconds per variant)."""
+        v = c_int()
+        us = (ctypes.c_float * 3)()
+        self._check(lib().gpe_batch_schedule(self.b, ctypes.byref(v), us, 3))
+        return v.value, list(us)

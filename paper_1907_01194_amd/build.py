@@ -10,11 +10,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpe.so")
-SOURCES = ["lap.hip", "pointwise.hip", "blas.hip", "mg.hip", "handle.cpp", "solver.cpp"]
+SOURCES = ["lap.hip", "batch_fft.hip", "pointwise.hip", "blas.hip", "mg.hip", "handle.cpp", "solver.cpp",
+           "batch.cpp"]
 ARCH = os.environ.get("GPE_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of every kernel.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+FLAGS = ["-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 

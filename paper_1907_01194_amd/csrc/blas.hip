@@ -3,12 +3,9 @@
 // componentwise scaling of the retractions (Sec. 6), CG vector updates and
 // precision conversions.  All reductions accumulate in FP64 whatever the
 // field precision.
-#include "common.h"
-#include "kernels.h"
+#include "batch_ops.h"
 
 namespace gpe {
-
-template <typename T> struct C7 { T v[7]; };
 
 // ----------------------------------------------------------------- finalize
 // One block per slot sums that slot's partials in a fixed order (so results
@@ -16,12 +13,10 @@ template <typename T> struct C7 { T v[7]; };
 // ticket, which it resets) applies the post-operation.
 constexpr int kFinThreads = 256;
 
-__global__ void __launch_bounds__(kFinThreads)
-finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, int nq, double* __restrict__ res,
-                int post, int F, double* gram, unsigned int* ticket) {
+__device__ void finalize_body(const double* __restrict__ part, size_t stride, const SlotCounts& nb, int nq,
+                              double* __restrict__ res, int post, int F, double* gram, unsigned int* ticket, int q) {
   __shared__ double red[kFinThreads / kWave];
   __shared__ bool last;
-  const int q = blockIdx.x;
   const double* pq = part + (size_t)q * stride;
   const int n = nb.nb[q];
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -45,7 +40,7 @@ finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, i
   }
   __syncthreads();
   if (!last || threadIdx.x != 0) return;
-  *ticket = 0u;   // every block of this launch has taken its ticket
+  *ticket = 0u;   // every block of this problem has taken its ticket
   __threadfence();
   const volatile double* out = res;
   const int K = 2 * F + 1;
@@ -76,35 +71,63 @@ finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, i
     const double det = a11 * a22 - a12 * a12;
     res[32] = (a22 * out[0] - a12 * out[1]) / det;
     res[33] = (a11 * out[1] - a12 * out[0]) / det;
-  } else if (post == POST_HVP_KAPPA) {
+  } else if (post == POST_HVP_KAPPA || post == POST_HVP_KAPPA_E) {
     double zlz = 0.0;
     for (int k = 6; k < nq; ++k) zlz += out[k];
-    res[34] = out[4] + zlz - out[32] * out[2] - out[33] * out[3];
+    double kappa = out[4] + zlz;
+    if (post == POST_HVP_KAPPA) kappa -= out[32] * out[2] + out[33] * out[3];
+    res[34] = kappa;
     res[35] = out[5];
   }
 }
 
+__global__ void __launch_bounds__(kFinThreads)
+finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, int nq, double* __restrict__ res,
+                int post, int F, double* gram, unsigned int* ticket) {
+  finalize_body(part, stride, nb, nq, res, post, F, gram, ticket, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+finalize_batched_kernel(const FinArgs* __restrict__ args, int nq, int post, int F) {
+  const FinArgs& a = args[blockIdx.y];
+  finalize_body(a.part, a.stride, a.nb, nq, a.res, post, F, a.gram, a.ticket, blockIdx.x);
+}
+
+static bool counts_ok(const SlotCounts& nb, int nq, size_t stride) {
+  if (nq < 1 || nq > kMaxQ || nq > (int)(sizeof(nb.nb) / sizeof(nb.nb[0]))) return false;
+  for (int q = 0; q < nq; ++q)
+    if (nb.nb[q] < 0 || (size_t)nb.nb[q] > stride) return false;
+  return true;
+}
+
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post, int F,
                     double* gram, unsigned int* ticket, hipStream_t st) {
-  if (nq < 1 || nq > kMaxQ || nq > (int)(sizeof(nb.nb) / sizeof(nb.nb[0]))) return hipErrorInvalidValue;
-  for (int q = 0; q < nq; ++q)
-    if (nb.nb[q] < 0 || (size_t)nb.nb[q] > stride) return hipErrorInvalidValue;
+  if (!counts_ok(nb, nq, stride)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(finalize_kernel, dim3(nq), dim3(kFinThreads), 0, st, part, stride, nb, nq, res, post, F, gram,
                      ticket);
   return hipGetLastError();
 }
 
+// The slot counts of the records are checked where the host builds them.
+hipError_t finalize_batched(const FinArgs* args, int nprob, int nq, int post, int F, hipStream_t st) {
+  if (nq < 1 || nq > kMaxQ || nprob < 1 || nprob > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_batched_kernel, dim3(nq, nprob), dim3(kFinThreads), 0, st, args, nq, post, F);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- projection
 template <typename T, typename TX, bool NORM>
-__global__ void __launch_bounds__(kRedThreads)
-project_kernel(int K, int F, const c_t<TX>* __restrict__ X, const c_t<T>* W, c_t<T>* out,
-               const double* __restrict__ coef, double* __restrict__ part, int nblk, size_t n) {
-  const double alpha = coef[0], beta = coef[1];
+__device__ void run_op(const ProjArgs<T, TX, NORM>& a, int blk, int nblk) {
+  const double alpha = a.coef ? a.coef[0] : a.c0, beta = a.coef ? a.coef[1] : a.c1;
+  auto X = reinterpret_cast<const c_t<TX>*>(a.X);
+  auto W = reinterpret_cast<const c_t<T>*>(a.W);
+  auto out = reinterpret_cast<c_t<T>*>(a.out);
+  const size_t n = a.npts;
   double acc[1] = {0.0};
-  const size_t total = (size_t)K * n;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+  const size_t total = (size_t)(2 * a.F + 1) * n;
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < total; e += (size_t)nblk * blockDim.x) {
     const int i = (int)(e / n);
-    const T c = (T)(alpha + beta * (double)(F - i));
+    const T c = (T)(alpha + beta * (double)(a.F - i));
     const c_t<TX> x = X[e];
     c_t<T> w = W[e];
     w.x -= c * (T)x.x;
@@ -112,38 +135,30 @@ project_kernel(int K, int F, const c_t<TX>* __restrict__ X, const c_t<T>* W, c_t
     out[e] = w;
     if (NORM) acc[0] += (double)cabs2(w);
   }
-  if (NORM) block_partials<1>(acc, part, nblk);
+  if (NORM) block_partials_any<1>(acc, a.part, nblk, blk);
 }
 
 template <typename T, typename TX>
 hipError_t project(int F, const void* X, const void* W, void* out, const double* coef, double* part, int nblk,
                    size_t npts, hipStream_t st) {
-  const int K = 2 * F + 1;
-  auto x = reinterpret_cast<const c_t<TX>*>(X);
-  auto w = reinterpret_cast<const c_t<T>*>(W);
-  auto o = reinterpret_cast<c_t<T>*>(out);
-  if (part)
-    hipLaunchKernelGGL((project_kernel<T, TX, true>), dim3(nblk), dim3(kRedThreads), 0, st, K, F, x, w, o, coef,
-                       part, nblk, npts);
-  else
-    hipLaunchKernelGGL((project_kernel<T, TX, false>), dim3(nblk), dim3(kRedThreads), 0, st, K, F, x, w, o, coef,
-                       part, nblk, npts);
-  return hipGetLastError();
+  if (part) return launch_single(ProjArgs<T, TX, true>{X, W, out, coef, 0.0, 0.0, part, npts, F}, nblk, st);
+  return launch_single(ProjArgs<T, TX, false>{X, W, out, coef, 0.0, 0.0, nullptr, npts, F}, nblk, st);
 }
 
 // ----------------------------------------------------------------- retraction support
 template <typename TU, typename TXI, int K>
-__global__ void __launch_bounds__(kRedThreads)
-comp_norms_kernel(const c_t<TU>* __restrict__ u, const c_t<TXI>* __restrict__ xi, double* __restrict__ part,
-                  int nblk, size_t n) {
+__device__ void run_op(const NormsArgs<TU, TXI, K>& a, int blk, int nblk) {
+  auto u = reinterpret_cast<const c_t<TU>*>(a.u);
+  auto xi = reinterpret_cast<const c_t<TXI>*>(a.xi);
+  const size_t n = a.npts;
   double acc[3 * K];
 #pragma unroll
   for (int q = 0; q < 3 * K; ++q) acc[q] = 0.0;
-  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
+  for (size_t j = (size_t)blk * blockDim.x + threadIdx.x; j < n; j += (size_t)nblk * blockDim.x) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const c_t<TU> a = u[i * n + j];
-      const double ax = a.x, ay = a.y;
+      const c_t<TU> av = u[i * n + j];
+      const double ax = av.x, ay = av.y;
       acc[i] += ax * ax + ay * ay;
       if (xi) {
         const c_t<TXI> b = xi[i * n + j];
@@ -153,35 +168,35 @@ comp_norms_kernel(const c_t<TU>* __restrict__ u, const c_t<TXI>* __restrict__ xi
       }
     }
   }
-  block_partials<3 * K>(acc, part, nblk);
+  block_partials_any<3 * K>(acc, a.part, nblk, blk);
 }
 
 template <typename TU, typename TXI>
 hipError_t comp_norms(int K, const void* u, const void* xi, double* part, int nblk, size_t npts, hipStream_t st) {
-  auto a = reinterpret_cast<const c_t<TU>*>(u);
-  auto b = reinterpret_cast<const c_t<TXI>*>(xi);
   switch (K) {
-    case 3: hipLaunchKernelGGL((comp_norms_kernel<TU, TXI, 3>), dim3(nblk), dim3(kRedThreads), 0, st, a, b, part, nblk, npts); break;
-    case 5: hipLaunchKernelGGL((comp_norms_kernel<TU, TXI, 5>), dim3(nblk), dim3(kRedThreads), 0, st, a, b, part, nblk, npts); break;
-    case 7: hipLaunchKernelGGL((comp_norms_kernel<TU, TXI, 7>), dim3(nblk), dim3(kRedThreads), 0, st, a, b, part, nblk, npts); break;
+    case 3: return launch_single(NormsArgs<TU, TXI, 3>{u, xi, part, npts}, nblk, st);
+    case 5: return launch_single(NormsArgs<TU, TXI, 5>{u, xi, part, npts}, nblk, st);
+    case 7: return launch_single(NormsArgs<TU, TXI, 7>{u, xi, part, npts}, nblk, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename TU, typename TXI, typename TO>
-__global__ void scale_comps_kernel(int K, const c_t<TU>* u, const c_t<TXI>* __restrict__ xi, double t, C7<double> s,
-                                   c_t<TO>* out, size_t n) {
-  const size_t total = (size_t)K * n;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+__device__ void run_op(const ScaleArgs<TU, TXI, TO>& a, int blk, int nblk) {
+  auto u = reinterpret_cast<const c_t<TU>*>(a.u);
+  auto xi = reinterpret_cast<const c_t<TXI>*>(a.xi);
+  auto out = reinterpret_cast<c_t<TO>*>(a.out);
+  const size_t n = a.npts;
+  const size_t total = (size_t)a.K * n;
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < total; e += (size_t)nblk * blockDim.x) {
     const int i = (int)(e / n);
-    const double si = s.v[i];
-    const c_t<TU> a = u[e];
-    double re = a.x, im = a.y;
+    const double si = a.s[i];
+    const c_t<TU> av = u[e];
+    double re = av.x, im = av.y;
     if (xi) {
       const c_t<TXI> b = xi[e];
-      re += t * (double)b.x;
-      im += t * (double)b.y;
+      re += a.t * (double)b.x;
+      im += a.t * (double)b.y;
     }
     c_t<TO> r;
     r.x = (TO)(si * re);
@@ -190,8 +205,8 @@ __global__ void scale_comps_kernel(int K, const c_t<TU>* u, const c_t<TXI>* __re
   }
 }
 
-static inline int grid_for(size_t total, int threads = 256) {
-  size_t g = (total + threads - 1) / threads;
+int elementwise_blocks(size_t total) {
+  size_t g = (total + kRedThreads - 1) / kRedThreads;
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   return (int)g;
@@ -200,87 +215,91 @@ static inline int grid_for(size_t total, int threads = 256) {
 template <typename TU, typename TXI, typename TO>
 hipError_t scale_comps(int K, const void* u, const void* xi, double t, const double* s, void* out, size_t npts,
                        hipStream_t st) {
-  C7<double> sv;
-  for (int i = 0; i < 7; ++i) sv.v[i] = i < K ? s[i] : 0.0;
-  hipLaunchKernelGGL((scale_comps_kernel<TU, TXI, TO>), dim3(grid_for((size_t)K * npts)), dim3(256), 0, st, K,
-                     reinterpret_cast<const c_t<TU>*>(u), reinterpret_cast<const c_t<TXI>*>(xi), t, sv,
-                     reinterpret_cast<c_t<TO>*>(out), npts);
-  return hipGetLastError();
+  ScaleArgs<TU, TXI, TO> a{u, xi, out, t, {0, 0, 0, 0, 0, 0, 0}, npts, K};
+  for (int i = 0; i < K && i < 7; ++i) a.s[i] = s[i];
+  return launch_single(a, elementwise_blocks((size_t)K * npts), st);
 }
 
 // ----------------------------------------------------------------- vector updates
 template <typename T>
-__global__ void axpby_kernel(T a, const c_t<T>* __restrict__ x, T b, c_t<T>* y, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+__device__ void run_op(const AxpbyArgs<T>& a, int blk, int nblk) {
+  auto x = reinterpret_cast<const c_t<T>*>(a.x);
+  auto y = reinterpret_cast<c_t<T>*>(a.y);
+  const T ca = (T)a.a, cb = (T)a.b;
+  const bool keep = a.b != 0.0;
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     const c_t<T> xv = x[e];
-    c_t<T> yv = y[e];
-    yv.x = a * xv.x + b * yv.x;
-    yv.y = a * xv.y + b * yv.y;
+    c_t<T> yv;
+    yv.x = ca * xv.x;
+    yv.y = ca * xv.y;
+    if (keep) {
+      const c_t<T> old = y[e];
+      yv.x += cb * old.x;
+      yv.y += cb * old.y;
+    }
     y[e] = yv;
   }
 }
 
 template <typename T>
 hipError_t axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((axpby_kernel<T>), dim3(grid_for(n)), dim3(256), 0, st, (T)a,
-                     reinterpret_cast<const c_t<T>*>(x), (T)b, reinterpret_cast<c_t<T>*>(y), n);
-  return hipGetLastError();
+  return launch_single(AxpbyArgs<T>{x, y, a, b, n}, elementwise_blocks(n), st);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads)
-cg_update_kernel(T a, const c_t<T>* __restrict__ p, const c_t<T>* __restrict__ q, c_t<T>* __restrict__ z,
-                 c_t<T>* __restrict__ r, double* __restrict__ part, int nblk, size_t n) {
+__device__ void run_op(const CgArgs<T>& a, int blk, int nblk) {
+  auto p = reinterpret_cast<const c_t<T>*>(a.p);
+  auto q = reinterpret_cast<const c_t<T>*>(a.q);
+  auto z = reinterpret_cast<c_t<T>*>(a.z);
+  auto r = reinterpret_cast<c_t<T>*>(a.r);
+  const T ca = (T)a.a;
   double acc[1] = {0.0};
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     const c_t<T> pv = p[e], qv = q[e];
     c_t<T> zv = z[e], rv = r[e];
-    zv.x += a * pv.x;
-    zv.y += a * pv.y;
-    rv.x += a * qv.x;
-    rv.y += a * qv.y;
+    zv.x += ca * pv.x;
+    zv.y += ca * pv.y;
+    rv.x += ca * qv.x;
+    rv.y += ca * qv.y;
     z[e] = zv;
     r[e] = rv;
     acc[0] += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
   }
-  block_partials<1>(acc, part, nblk);
+  block_partials_any<1>(acc, a.part, nblk, blk);
 }
 
 template <typename T>
 hipError_t cg_update(double a, const void* p, const void* q, void* z, void* r, double* part, int nblk, size_t n,
                      hipStream_t st) {
-  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk), dim3(kRedThreads), 0, st, (T)a,
-                     reinterpret_cast<const c_t<T>*>(p), reinterpret_cast<const c_t<T>*>(q),
-                     reinterpret_cast<c_t<T>*>(z), reinterpret_cast<c_t<T>*>(r), part, nblk, n);
-  return hipGetLastError();
+  return launch_single(CgArgs<T>{p, q, z, r, part, a, n}, nblk, st);
 }
 
 template <typename TA, typename TB>
-__global__ void __launch_bounds__(kRedThreads)
-dot_kernel(const c_t<TA>* __restrict__ a, const c_t<TB>* __restrict__ b, double* __restrict__ part, int nblk,
-           size_t n) {
+__device__ void run_op(const DotArgs<TA, TB>& a, int blk, int nblk) {
+  auto x = reinterpret_cast<const c_t<TA>*>(a.a);
+  auto y = reinterpret_cast<const c_t<TB>*>(a.b);
   double acc[1] = {0.0};
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const c_t<TA> av = a[e];
-    const c_t<TB> bv = b[e];
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
+    const c_t<TA> av = x[e];
+    const c_t<TB> bv = y[e];
     acc[0] += (double)av.x * (double)bv.x + (double)av.y * (double)bv.y;
   }
-  block_partials<1>(acc, part, nblk);
+  block_partials_any<1>(acc, a.part, nblk, blk);
 }
 
 template <typename TA, typename TB>
 hipError_t dot(const void* a, const void* b, double* part, int nblk, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((dot_kernel<TA, TB>), dim3(nblk), dim3(kRedThreads), 0, st,
-                     reinterpret_cast<const c_t<TA>*>(a), reinterpret_cast<const c_t<TB>*>(b), part, nblk, n);
-  return hipGetLastError();
+  return launch_single(DotArgs<TA, TB>{a, b, part, n}, nblk, st);
 }
 
 template <typename TA, typename TB, typename TO>
-__global__ void diff_kernel(const c_t<TA>* __restrict__ a, const c_t<TB>* __restrict__ b, c_t<TO>* __restrict__ o,
-                            size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const c_t<TA> av = a[e];
-    const c_t<TB> bv = b[e];
+__device__ void run_op(const DiffArgs<TA, TB, TO>& a, int blk, int nblk) {
+  auto x = reinterpret_cast<const c_t<TA>*>(a.a);
+  auto y = reinterpret_cast<const c_t<TB>*>(a.b);
+  auto o = reinterpret_cast<c_t<TO>*>(a.out);
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
+    const c_t<TA> av = x[e];
+    const c_t<TB> bv = y[e];
     c_t<TO> r;
     r.x = (TO)((double)av.x - (double)bv.x);
     r.y = (TO)((double)av.y - (double)bv.y);
@@ -290,36 +309,66 @@ __global__ void diff_kernel(const c_t<TA>* __restrict__ a, const c_t<TB>* __rest
 
 template <typename TA, typename TB, typename TO>
 hipError_t diff(const void* a, const void* b, void* out, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((diff_kernel<TA, TB, TO>), dim3(grid_for(n)), dim3(256), 0, st,
-                     reinterpret_cast<const c_t<TA>*>(a), reinterpret_cast<const c_t<TB>*>(b),
-                     reinterpret_cast<c_t<TO>*>(out), n);
-  return hipGetLastError();
+  return launch_single(DiffArgs<TA, TB, TO>{a, b, out, n}, elementwise_blocks(n), st);
 }
 
 template <typename TI, typename TO>
-__global__ void convert_kernel(const c_t<TI>* __restrict__ a, c_t<TO>* __restrict__ o, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const c_t<TI> v = a[e];
+__device__ void run_op(const ConvArgs<TI, TO>& a, int blk, int nblk) {
+  auto x = reinterpret_cast<const c_t<TI>*>(a.src);
+  auto o = reinterpret_cast<c_t<TO>*>(a.dst);
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     c_t<TO> r;
-    r.x = (TO)v.x;
-    r.y = (TO)v.y;
+    if (x) {
+      const c_t<TI> v = x[e];
+      r.x = (TO)v.x;
+      r.y = (TO)v.y;
+    } else {
+      r.x = TO(0);
+      r.y = TO(0);
+    }
     o[e] = r;
   }
 }
 
 hipError_t to_c64(const void* src, void* dst, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid_for(n)), dim3(256), 0, st,
-                     reinterpret_cast<const double2*>(src), reinterpret_cast<float2*>(dst), n);
-  return hipGetLastError();
+  return launch_single(ConvArgs<double, float>{src, dst, n}, elementwise_blocks(n), st);
 }
 
 hipError_t to_c128(const void* src, void* dst, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, st,
-                     reinterpret_cast<const float2*>(src), reinterpret_cast<double2*>(dst), n);
-  return hipGetLastError();
+  return launch_single(ConvArgs<float, double>{src, dst, n}, elementwise_blocks(n), st);
 }
 
 // ----------------------------------------------------------------- instantiations
+GPE_OP(ProjArgs<double, double, true>)
+GPE_OP(ProjArgs<double, double, false>)
+GPE_OP(ProjArgs<float, float, true>)
+GPE_OP(ProjArgs<float, float, false>)
+GPE_OP(NormsArgs<double, double, 3>)
+GPE_OP(NormsArgs<double, double, 5>)
+GPE_OP(NormsArgs<double, double, 7>)
+GPE_OP(NormsArgs<double, float, 3>)
+GPE_OP(NormsArgs<double, float, 5>)
+GPE_OP(NormsArgs<double, float, 7>)
+GPE_OP(NormsArgs<float, float, 3>)
+GPE_OP(NormsArgs<float, float, 5>)
+GPE_OP(NormsArgs<float, float, 7>)
+GPE_OP(ScaleArgs<double, double, double>)
+GPE_OP(ScaleArgs<double, float, double>)
+GPE_OP(ScaleArgs<float, float, float>)
+GPE_OP(AxpbyArgs<double>)
+GPE_OP(AxpbyArgs<float>)
+GPE_OP(CgArgs<double>)
+GPE_OP(CgArgs<float>)
+GPE_OP(DotArgs<double, double>)
+GPE_OP(DotArgs<float, float>)
+GPE_OP(DotArgs<double, float>)
+GPE_OP(DiffArgs<double, double, double>)
+GPE_OP(DiffArgs<double, double, float>)
+GPE_OP(ConvArgs<double, float>)
+GPE_OP(ConvArgs<float, double>)
+GPE_OP(ConvArgs<double, double>)
+GPE_OP(ConvArgs<float, float>)
+
 template hipError_t project<double, double>(int, const void*, const void*, void*, const double*, double*, int, size_t, hipStream_t);
 template hipError_t project<float, float>(int, const void*, const void*, void*, const double*, double*, int, size_t, hipStream_t);
 template hipError_t comp_norms<double, double>(int, const void*, const void*, double*, int, size_t, hipStream_t);

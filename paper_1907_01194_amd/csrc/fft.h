@@ -1,0 +1,410 @@
+// Device building blocks of the spectral Laplacian passes (Sec. 3, eq.
+// discrete:laplace): the mixed radix-8/4/3/2 Stockham line transforms in LDS,
+// one axis pass over a block of lines, and the fused x pass of the
+// Hessian-vector product (pointwise Hessian terms of Sec. 3 plus L_x).  The
+// bodies take their workgroup index explicitly so that one batched launch
+// can run them for many problems (batch_fft.hip) as well as one (lap.hip).
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+#include "spin.h"
+
+namespace gpe {
+
+struct RadixPlan {
+  int S;
+  int r[12];
+  int maxr;
+};
+
+constexpr RadixPlan make_plan(int N) {
+  RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, 1};
+  int m = N;
+  while (m % 3 == 0) { p.r[p.S++] = 3; m /= 3; }
+  while (m % 8 == 0) { p.r[p.S++] = 8; m /= 8; }
+  if (m % 4 == 0) { p.r[p.S++] = 4; m /= 4; }
+  if (m % 2 == 0) { p.r[p.S++] = 2; m /= 2; }
+  for (int i = 0; i < p.S; ++i)
+    if (p.r[i] > p.maxr) p.maxr = p.r[i];
+  return p;
+}
+
+constexpr int plan_prefix(RadixPlan p, int s) {
+  int v = 1;
+  for (int i = 0; i < s; ++i) v *= p.r[i];
+  return v;
+}
+
+template <int N> struct Geo {
+  static constexpr RadixPlan P = make_plan(N);
+  static constexpr int TPL = N / P.maxr;                       // threads per line
+  static constexpr int LPB0 = (256 / TPL) > 0 ? 256 / TPL : 1;
+  static constexpr int LPB = LPB0 >= 128 ? 128 : LPB0 >= 64 ? 64 : LPB0 >= 32 ? 32 : LPB0 >= 16 ? 16
+                           : LPB0 >= 8 ? 8 : LPB0 >= 4 ? 4 : LPB0 >= 2 ? 2 : 1;   // power of two
+  static constexpr int THREADS = LPB * TPL;
+};
+
+// multiply by -i (forward) or +i (inverse)
+template <bool FWD, typename T2> __device__ __forceinline__ T2 mul_mi(T2 a) {
+  return FWD ? mk<T2>(a.y, -a.x) : mk<T2>(-a.y, a.x);
+}
+
+template <int R, bool FWD, typename T2> struct Dft;
+
+template <bool FWD, typename T2> struct Dft<2, FWD, T2> {
+  __device__ static __forceinline__ void run(T2* a) {
+    T2 t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  }
+};
+
+template <bool FWD, typename T2> struct Dft<4, FWD, T2> {
+  __device__ static __forceinline__ void run(T2* a) {
+    T2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    T2 t2 = cadd(a[1], a[3]), t3 = mul_mi<FWD>(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+template <bool FWD, typename T2> struct Dft<8, FWD, T2> {
+  __device__ static __forceinline__ void run(T2* a) {
+    using T = decltype(T2::x);
+    T2 e[4] = {a[0], a[2], a[4], a[6]};
+    T2 o[4] = {a[1], a[3], a[5], a[7]};
+    Dft<4, FWD, T2>::run(e);
+    Dft<4, FWD, T2>::run(o);
+    const T s = (T)0.70710678118654752440;
+    // o1 *= W8, o2 *= W8^2 = -+i, o3 *= W8^3
+    T2 o1 = FWD ? mk<T2>(s * (o[1].x + o[1].y), s * (o[1].y - o[1].x))
+                : mk<T2>(s * (o[1].x - o[1].y), s * (o[1].y + o[1].x));
+    T2 o2 = mul_mi<FWD>(o[2]);
+    T2 o3 = FWD ? mk<T2>(s * (o[3].y - o[3].x), -s * (o[3].x + o[3].y))
+                : mk<T2>(-s * (o[3].x + o[3].y), s * (o[3].x - o[3].y));
+    a[0] = cadd(e[0], o[0]);
+    a[4] = csub(e[0], o[0]);
+    a[1] = cadd(e[1], o1);
+    a[5] = csub(e[1], o1);
+    a[2] = cadd(e[2], o2);
+    a[6] = csub(e[2], o2);
+    a[3] = cadd(e[3], o3);
+    a[7] = csub(e[3], o3);
+  }
+};
+
+template <bool FWD, typename T2> struct Dft<3, FWD, T2> {
+  __device__ static __forceinline__ void run(T2* a) {
+    using T = decltype(T2::x);
+    const T c = (T)0.86602540378443864676;  // sqrt(3)/2
+    T2 s = cadd(a[1], a[2]);
+    T2 d = csub(a[1], a[2]);
+    T2 m = mk<T2>(a[0].x - (T)0.5 * s.x, a[0].y - (T)0.5 * s.y);
+    T2 jd = mul_mi<FWD>(mk<T2>(c * d.x, c * d.y));   // -+ i sqrt(3)/2 d
+    a[0] = cadd(a[0], s);
+    a[1] = cadd(m, jd);
+    a[2] = csub(m, jd);
+  }
+};
+
+enum { SRC_GLOBAL = 0, SRC_LDS = 1 };
+enum { DST_LDS = 0, DST_GLOBAL = 1 };
+
+struct LineCtx {
+  size_t goff;      // global element offset of this thread's line
+  int gstride;      // element stride along the line in global memory
+  int lbase;        // LDS element offset of this thread's line
+  int lstride;      // element stride along the line in LDS
+  int tl;           // thread index within the line
+  bool valid;       // line exists
+};
+
+// Epilogue of the last inverse pass: out = acc + val - pc * X (pc = 0: no projection).
+template <typename T> struct Epi {
+  const c_t<T>* acc;
+  const c_t<T>* X;
+  T pc;
+};
+
+template <typename T, int N, int s, bool FWD, int SRC, int DST>
+__device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* lds,
+                                      const c_t<T>* tw, c_t<T>* __restrict__ gout,
+                                      const Epi<T>& epi, const LineCtx& lc, T lamc, T invn, double& pars) {
+  using T2 = c_t<T>;
+  constexpr RadixPlan P = Geo<N>::P;
+  constexpr int R = P.r[s];
+  constexpr int Ns = plan_prefix(P, s);
+  constexpr int B = N / R;
+  constexpr int TPL = Geo<N>::TPL;
+  constexpr int NB = (B + TPL - 1) / TPL;
+  constexpr bool LAST_FWD = FWD && (s == P.S - 1);
+  T2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = lc.tl + i * TPL;
+    if (lc.valid && (B % TPL == 0 || b < B)) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int j = b + r * B;
+        v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[lc.lbase + j * lc.lstride];
+      }
+    }
+  }
+  if (SRC == SRC_LDS) __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = lc.tl + i * TPL;
+    if (lc.valid && (B % TPL == 0 || b < B)) {
+      const int k = b % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = tw[(r * k * (N / (Ns * R))) % N];
+          if (!FWD) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      Dft<R, FWD, T2>::run(v[i]);
+      const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = base + r * Ns;
+        T2 val = v[i][r];
+        if (LAST_FWD) {
+          const int p = idx < N / 2 ? idx : idx - N;
+          const T lam = lamc * (T)p;
+          const T sc = lam * lam * invn;
+          pars += (double)sc * (double)cabs2(val);   // Parseval: <Z, L_a Z> = sum lambda^2/n |Z^|^2
+          val = cscale(val, sc);
+        }
+        if (DST == DST_LDS) {
+          lds[lc.lbase + idx * lc.lstride] = val;
+        } else {
+          const size_t g = lc.goff + (size_t)idx * lc.gstride;
+          T2 o = epi.acc ? cadd(epi.acc[g], val) : val;
+          if (epi.X) {
+            const T2 xv = epi.X[g];
+            o.x -= epi.pc * xv.x;
+            o.y -= epi.pc * xv.y;
+          }
+          gout[g] = o;
+        }
+      }
+    }
+  }
+  if (DST == DST_LDS) __syncthreads();
+}
+
+template <typename T, int N, int s>
+__device__ __forceinline__ void fwd_stages(const c_t<T>* gin, c_t<T>* lds, const c_t<T>* tw,
+                                           const LineCtx& lc, T lamc, T invn, double& pars) {
+  constexpr int S = Geo<N>::P.S;
+  const Epi<T> none{nullptr, nullptr, T(0)};
+  if constexpr (s < S) {
+    if constexpr (s == 0)
+      stage<T, N, 0, true, SRC_GLOBAL, DST_LDS>(gin, lds, tw, nullptr, none, lc, lamc, invn, pars);
+    else
+      stage<T, N, s, true, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, lamc, invn, pars);
+    fwd_stages<T, N, s + 1>(gin, lds, tw, lc, lamc, invn, pars);
+  }
+}
+
+// LAST_TO_GLOBAL: the last inverse pass writes global memory through the
+// epilogue; otherwise it writes the result back to LDS.
+template <typename T, int N, int s, bool LAST_TO_GLOBAL>
+__device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>* gout, const Epi<T>& epi,
+                                           const LineCtx& lc) {
+  constexpr int S = Geo<N>::P.S;
+  const Epi<T> none{nullptr, nullptr, T(0)};
+  double dummy = 0.0;
+  if constexpr (s < S) {
+    if constexpr (s == S - 1 && LAST_TO_GLOBAL)
+      stage<T, N, s, false, SRC_LDS, DST_GLOBAL>(nullptr, lds, tw, gout, epi, lc, T(0), T(0), dummy);
+    else
+      stage<T, N, s, false, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, T(0), T(0), dummy);
+    inv_stages<T, N, s + 1, LAST_TO_GLOBAL>(lds, tw, gout, epi, lc);
+  }
+}
+
+// One axis pass for every line of every component: out = acc + L_a(in)
+// [- (coef[0] + coef[1] l) X], with the Parseval sum <in, L_a in> per workgroup
+// in part[slot * stride + wg] when part != null.
+// Threads at or beyond Geo<N>::THREADS (a batched launch sized for another
+// N) take no line.
+template <typename T, int N>
+__device__ __forceinline__ void lap_body(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
+                                         const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F,
+                                         size_t npts, const c_t<T>* __restrict__ X, const double* __restrict__ coef,
+                                         double* __restrict__ part, size_t stride, int slot, long blk) {
+  using T2 = c_t<T>;
+  constexpr int TPL = Geo<N>::TPL;
+  constexpr int LPB = Geo<N>::LPB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* tw = reinterpret_cast<T2*>(smem_raw);
+  T2* lds = tw + N;
+
+  const int t = threadIdx.x;
+  for (int m = t; m < N; m += blockDim.x) tw[m] = twg[m];
+
+  LineCtx lc;
+  int ln;
+  if (inner == 1) {
+    lc.tl = t % TPL;
+    ln = t / TPL;
+    lc.lstride = 1;
+    lc.lbase = ln * (N + 1);
+  } else {
+    ln = t % LPB;
+    lc.tl = t / LPB;
+    lc.lstride = LPB;
+    lc.lbase = ln;
+  }
+  const long L = blk * LPB + ln;
+  lc.valid = t < Geo<N>::THREADS && L < nlines;
+  const long o = L / inner;
+  const long i = L % inner;
+  lc.goff = (size_t)o * N * inner + i;
+  lc.gstride = inner;
+  const T invn = T(1) / T(N);
+  Epi<T> epi{acc, nullptr, T(0)};
+  if (X && lc.valid) {
+    const int comp = (int)(lc.goff / npts);          // a line never crosses a component
+    epi.X = X;
+    epi.pc = (T)(coef[0] + coef[1] * (double)(F - comp));
+  }
+  double pars = 0.0;
+  // Stage 0 reads global memory and uses no twiddles; the barrier that ends it
+  // also publishes the twiddle table.
+  fwd_stages<T, N, 0>(in, lds, tw, lc, lamc, invn, pars);
+  inv_stages<T, N, 0, true>(lds, tw, out, epi, lc);
+  if (part) {
+    double a[1] = {pars};
+    block_partials_any<1>(a, part + (size_t)slot * stride, 0, blk);
+  }
+}
+
+// Fused x pass of the Hessian-vector product: RPB x-rows, all K components.
+// Schedule variant VAR: 0 = half the default rows per workgroup, 1 = default
+// (about 256 threads), 2 = twice the default (if it fits 1024 threads).
+template <int N, int K, int VAR = 1> struct XGeo {
+  static constexpr int TPL = Geo<N>::TPL;
+  static constexpr int R0 = 256 / (K * TPL);
+  static constexpr int RD = R0 >= 16 ? 16 : R0 >= 8 ? 8 : R0 >= 4 ? 4 : R0 >= 2 ? 2 : 1;
+  static constexpr int RPB = VAR == 0 ? (RD > 1 ? RD / 2 : 1)
+                           : VAR == 1 ? RD
+                           : (2 * RD * K * TPL <= 1024 ? 2 * RD : RD);
+  static constexpr int LINES = RPB * K;
+  static constexpr int THREADS = ((LINES * TPL + 63) / 64) * 64;
+};
+
+template <typename T, int N, int F, int VAR>
+__device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z,
+                                           const c_t<T>* __restrict__ Y, const T* __restrict__ V,
+                                           c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
+                                           size_t npts, T lamc, const PwParams& p, double* __restrict__ part,
+                                           size_t stride, long blk) {
+  using T2 = c_t<T>;
+  constexpr int K = 2 * F + 1;
+  constexpr int TPL = Geo<N>::TPL;
+  constexpr int RPB = XGeo<N, K, VAR>::RPB;
+  constexpr int LINES = XGeo<N, K, VAR>::LINES;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* tw = reinterpret_cast<T2*>(smem_raw);
+  T2* lds = tw + N;
+  const int t = threadIdx.x;
+  for (int m = t; m < N; m += blockDim.x) tw[m] = twg[m];
+  const long row0 = blk * RPB;
+
+  // ---- c64: prefetch the pointwise operands of this thread's first point so
+  // their latency hides behind the transforms below (in FP64 the extra live
+  // registers would cost more occupancy than the overlap gains)
+  constexpr bool kPrefetch = sizeof(T) == 4;
+  int pt = t;
+  bool have = pt < RPB * N && row0 + pt / N < nrows;
+  T2 x[K], z[K], y[K];
+  T vj = T(0);
+  size_t j = have ? (size_t)(row0 + pt / N) * N + pt % N : 0;
+  auto load_point = [&]() {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      x[i] = X[i * npts + j];
+      z[i] = Z[i * npts + j];
+      y[i] = Y[i * npts + j];
+    }
+    vj = V[j];
+  };
+  if (kPrefetch && have) load_point();
+
+  // ---- L_x Z for the RPB rows of every component, left in LDS
+  LineCtx lc;
+  const int ls = t / TPL;                 // line slot = comp * RPB + row
+  lc.tl = t % TPL;
+  const int comp = ls / RPB, r = ls % RPB;
+  lc.valid = ls < LINES && row0 + r < nrows;
+  lc.goff = (size_t)comp * npts + (size_t)(row0 + r) * N;
+  lc.gstride = 1;
+  lc.lbase = ls * (N + 1);
+  lc.lstride = 1;
+  const T invn = T(1) / T(N);
+  double pars = 0.0;
+  const Epi<T> none{nullptr, nullptr, T(0)};
+  fwd_stages<T, N, 0>(Z, lds, tw, lc, lamc, invn, pars);
+  inv_stages<T, N, 0, false>(lds, tw, nullptr, none, lc);
+
+  // ---- pointwise Hessian terms, W = L_x Z + q
+  T zcoef[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) zcoef[i] = (T)p.zc[i];
+  double acc[7] = {0, 0, 0, 0, 0, 0, pars};
+  auto point = [&](int rr, int xx) {
+    double xy = 0, lxy = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double c = (double)cdotr(y[i], z[i]);     // <(LX)_i, Z_i> = <X_i, (LZ)_i>
+      xy += c;
+      lxy += (double)(F - i) * c;
+    }
+    T2 q[K];
+    hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) { q[i] = qi; });
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const T2 lz = lds[(i * RPB + rr) * (N + 1) + xx];
+      W[i * npts + j] = cadd(lz, q[i]);
+      const double xq = (double)cdotr(x[i], q[i]);
+      const double xz = (double)cdotr(x[i], z[i]);
+      const double l = (double)(F - i);
+      xy += xq;
+      lxy += l * xq;
+      acc[2] += xz;
+      acc[3] += l * xz;
+      acc[4] += (double)cdotr(z[i], q[i]);
+      acc[5] += (double)cabs2(z[i]);
+    }
+    acc[0] += xy;
+    acc[1] += lxy;
+  };
+  if constexpr (kPrefetch) {
+    while (have) {
+      point(pt / N, pt % N);
+      pt += blockDim.x;
+      have = pt < RPB * N && row0 + pt / N < nrows;
+      if (have) {
+        j = (size_t)(row0 + pt / N) * N + pt % N;
+        load_point();
+      }
+    }
+  } else {
+    for (pt = t; pt < RPB * N; pt += blockDim.x) {
+      if (row0 + pt / N >= nrows) break;
+      j = (size_t)(row0 + pt / N) * N + pt % N;
+      load_point();
+      point(pt / N, pt % N);
+    }
+  }
+  block_partials_any<7>(acc, part, stride, blk);
+}
+
+}  // namespace gpe

@@ -58,24 +58,42 @@ gpe_status laplacian(gpe_handle* h, const void* in, void* out) {
 template gpe_status laplacian<double>(gpe_handle*, const void*, void*);
 template gpe_status laplacian<float>(gpe_handle*, const void*, void*);
 
-gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout) {
+gpe_status finalize_enq(gpe_handle* h, int nq, int post, double* gram) {
   SlotCounts nb;
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = h->nblk;
   GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, h->ticket, h->st));
-  GPE_HIP(h, hipMemcpyAsync(h->hres, h->res, sizeof(double) * nout, hipMemcpyDeviceToHost, h->st));
-  GPE_HIP(h, hipStreamSynchronize(h->st));
-  for (int i = 0; i < nout; ++i)
-    if (!std::isfinite(h->hres[i])) return fail(h, GPE_ENUMERIC, "NaN or Inf in a reduction");
   return GPE_OK;
 }
 
-gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, double* E, double* ag, double* bg) {
+gpe_status fetch(gpe_handle* h) {
+  GPE_HIP(h, hipMemcpyAsync(h->hres, h->res, sizeof(double) * kResDoubles, hipMemcpyDeviceToHost, h->st));
+  GPE_HIP(h, hipStreamSynchronize(h->st));
+  return GPE_OK;
+}
+
+static gpe_status finite(gpe_handle* h, const double* v, int n, const char* what) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return fail(h, GPE_ENUMERIC, std::string("NaN or Inf in ") + what);
+  return GPE_OK;
+}
+
+gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout) {
+  GPE_TRY(finalize_enq(h, nq, post, gram));
+  GPE_TRY(fetch(h));
+  return finite(h, h->hres, nout, "a reduction");
+}
+
+gpe_status eval_enq(gpe_handle* h, const void* X, void* G, double* gram) {
   GPE_TRY(laplacian<double>(h, X, h->T64));
   GPE_KT(h, KK_PW_GRAD, pw_grad<double>(h->F, X, h->T64, h->V64, G, h->part, h->nblk, h->npts, h->pw, h->st));
+  return finalize_enq(h, 1 + 2 * h->K, G ? POST_GRAD : POST_NONE, G ? gram : nullptr);
+}
+
+gpe_status eval_read(gpe_handle* h, bool grad, double* E, double* ag, double* bg) {
   const int nq = 1 + 2 * h->K;
-  if (G) {
-    GPE_TRY(reduce_to_host(h, nq, POST_GRAD, gram, nq + 2));
-    const double* r = h->hres;
+  const double* r = h->hres;
+  GPE_TRY(finite(h, r, grad ? nq + 2 : 1, "the energy or gradient"));
+  if (grad) {
     double a11 = 0, a12 = 0, a22 = 0;
     for (int i = 0; i < h->K; ++i) {
       const double l = h->F - i;
@@ -87,23 +105,35 @@ gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, doubl
       return fail(h, GPE_EDEGEN, "degenerate point: u^T Gamma^2 u u^T u - (u^T Gamma u)^2 <= 0");
     if (ag) *ag = r[nq];
     if (bg) *bg = r[nq + 1];
-  } else {
-    GPE_TRY(reduce_to_host(h, nq, POST_NONE, nullptr, 1));
   }
-  if (E) *E = h->hres[0];
+  if (E) *E = r[0];
+  return GPE_OK;
+}
+
+gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, double* E, double* ag, double* bg) {
+  GPE_TRY(eval_enq(h, X, G, gram));
+  GPE_TRY(fetch(h));
+  return eval_read(h, G != nullptr, E, ag, bg);
+}
+
+gpe_status pgrad_enq(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg) {
+  GPE_KT(h, KK_PROJECT,
+         launch_single(ProjArgs<double, double, true>{X, G, gR, nullptr, ag, bg, h->part, h->npts, h->F}, h->nblk,
+                       h->st));
+  return finalize_enq(h, 1, POST_NONE, nullptr);
+}
+
+gpe_status pgrad_read(gpe_handle* h, double* gnorm) {
+  GPE_TRY(finite(h, h->hres, 1, "the gradient norm"));
+  if (gnorm) *gnorm = std::sqrt(h->hres[0]);
   return GPE_OK;
 }
 
 gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg,
                         double* gnorm) {
-  h->hres[0] = ag;
-  h->hres[1] = bg;
-  // coefficients travel through res[40..41] on the device
-  GPE_HIP(h, hipMemcpyAsync(h->res + 40, h->hres, 2 * sizeof(double), hipMemcpyHostToDevice, h->st));
-  GPE_KT(h, KK_PROJECT, (project<double, double>(h->F, X, G, gR, h->res + 40, h->part, h->nblk, h->npts, h->st)));
-  GPE_TRY(reduce_to_host(h, 1, POST_NONE, nullptr, 1));
-  if (gnorm) *gnorm = std::sqrt(h->hres[0]);
-  return GPE_OK;
+  GPE_TRY(pgrad_enq(h, X, G, gR, ag, bg));
+  GPE_TRY(fetch(h));
+  return pgrad_read(h, gnorm);
 }
 
 gpe_status adopt_point(gpe_handle* h) {
@@ -132,8 +162,6 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   double* coef = h->res + 32;
   if (riem)
     GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, h->st));
-  else
-    GPE_HIP(h, hipMemsetAsync(coef, 0, 2 * sizeof(double), h->st));
   int nq = 7;
   if (h->dim == 1) {
     if (riem) GPE_KT(h, KK_PROJECT, (project<T, T>(h->F, Xw, HZ, HZ, coef, nullptr, h->nblk, h->npts, h->st)));
@@ -146,7 +174,8 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
       nq = 7 + a;
     }
   }
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, POST_HVP_KAPPA, h->F, h->gram_pt, h->ticket, h->st));
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E, h->F,
+                                  h->gram_pt, h->ticket, h->st));
   return GPE_OK;
 }
 
@@ -197,36 +226,56 @@ gpe_status tune_xpass(gpe_handle* h) {
   return h->prec == GPE_FP64 ? tune_xpass_t<double>(h) : tune_xpass_t<float>(h);
 }
 
-gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
-  if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
+PwParams hvp_params(const gpe_handle* h, bool riem, double sigma) {
   PwParams p = h->pw;
   for (int i = 0; i < 7; ++i) p.zc[i] = (riem && i < h->K) ? sigma - h->alpha_g - h->beta_g * (h->F - i) : 0.0;
-  if (h->prec == GPE_FP64) GPE_TRY(hvp_t<double>(h, Z, HZ, riem, p));
-  else GPE_TRY(hvp_t<float>(h, Z, HZ, riem, p));
-  if (kappa || zz) {
-    GPE_HIP(h, hipMemcpyAsync(h->hres, h->res + 34, 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    GPE_HIP(h, hipStreamSynchronize(h->st));
-    if (!std::isfinite(h->hres[0]) || !std::isfinite(h->hres[1]))
-      return fail(h, GPE_ENUMERIC, "NaN or Inf in the Hessian-vector product");
-    if (kappa) *kappa = h->hres[0];
-    if (zz) *zz = h->hres[1];
+  return p;
+}
+
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma) {
+  if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
+  const PwParams p = hvp_params(h, riem, sigma);
+  if (h->prec == GPE_FP64) return hvp_t<double>(h, Z, HZ, riem, p);
+  return hvp_t<float>(h, Z, HZ, riem, p);
+}
+
+gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz) {
+  GPE_TRY(finite(h, h->hres + 34, 2, "the Hessian-vector product"));
+  if (kappa) *kappa = h->hres[34];
+  if (zz) *zz = h->hres[35];
+  return GPE_OK;
+}
+
+gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
+  GPE_TRY(hvp_enq(h, Z, HZ, riem, sigma));
+  if (!kappa && !zz) return GPE_OK;
+  GPE_TRY(fetch(h));
+  return hvp_read(h, kappa, zz);
+}
+
+gpe_status norms_enq(gpe_handle* h, const void* u, const void* xi, bool xi32) {
+  if (xi32)
+    GPE_KT(h, KK_NORMS, (comp_norms<double, float>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
+  else
+    GPE_KT(h, KK_NORMS, (comp_norms<double, double>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
+  return finalize_enq(h, 3 * h->K, POST_NONE, nullptr);
+}
+
+gpe_status norms_read(gpe_handle* h, bool has_xi, RetractNorms* rn) {
+  const int K = h->K;
+  GPE_TRY(finite(h, h->hres, 3 * K, "the component norms"));
+  for (int i = 0; i < K; ++i) {
+    rn->uu[i] = h->hres[i];
+    rn->ux[i] = has_xi ? h->hres[K + i] : 0.0;
+    rn->xx[i] = has_xi ? h->hres[2 * K + i] : 0.0;
   }
   return GPE_OK;
 }
 
 gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32, RetractNorms* rn) {
-  if (xi32)
-    GPE_KT(h, KK_NORMS, (comp_norms<double, float>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
-  else
-    GPE_KT(h, KK_NORMS, (comp_norms<double, double>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
-  const int K = h->K;
-  GPE_TRY(reduce_to_host(h, 3 * K, POST_NONE, nullptr, 3 * K));
-  for (int i = 0; i < K; ++i) {
-    rn->uu[i] = h->hres[i];
-    rn->ux[i] = xi ? h->hres[K + i] : 0.0;
-    rn->xx[i] = xi ? h->hres[2 * K + i] : 0.0;
-  }
-  return GPE_OK;
+  GPE_TRY(norms_enq(h, u, xi, xi32));
+  GPE_TRY(fetch(h));
+  return norms_read(h, xi != nullptr, rn);
 }
 
 // Projective retraction (Sec. 6.1): sigma_l = 1/(sqrt(s)(1 - (l-M) r)) on
@@ -336,14 +385,19 @@ gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* si
   }
 }
 
-gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32, double t,
-                         int kind, void* out) {
-  double a[7], sig[7];
+gpe_status retract_sigma_at(gpe_handle* h, const RetractNorms& rn, double t, int kind, double* sig) {
+  double a[7];
   for (int i = 0; i < h->K; ++i) {
     a[i] = rn.uu[i] + 2.0 * t * rn.ux[i] + t * t * rn.xx[i];   // ||u_i + t xi_i||^2
     if (a[i] < 0) a[i] = 0;
   }
-  GPE_TRY(retraction_sigma(h, a, kind, sig));
+  return retraction_sigma(h, a, kind, sig);
+}
+
+gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32, double t,
+                         int kind, void* out) {
+  double sig[7];
+  GPE_TRY(retract_sigma_at(h, rn, t, kind, sig));
   if (xi32)
     GPE_KT(h, KK_SCALE, (scale_comps<double, float, double>(h->K, u, xi, t, sig, out, h->npts, h->st)));
   else
@@ -351,14 +405,30 @@ gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, c
   return GPE_OK;
 }
 
-gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out) {
+gpe_status dot_enq(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n) {
   if (!a32 && !b32) GPE_KT(h, KK_VECTOR, (dot<double, double>(a, b, h->part, h->nblk, n, h->st)));
   else if (a32 && b32) GPE_KT(h, KK_VECTOR, (dot<float, float>(a, b, h->part, h->nblk, n, h->st)));
   else if (!a32 && b32) GPE_KT(h, KK_VECTOR, (dot<double, float>(a, b, h->part, h->nblk, n, h->st)));
   else GPE_KT(h, KK_VECTOR, (dot<double, float>(b, a, h->part, h->nblk, n, h->st)));
-  GPE_TRY(reduce_to_host(h, 1, POST_NONE, nullptr, 1));
+  return finalize_enq(h, 1, POST_NONE, nullptr);
+}
+
+gpe_status dot_read(gpe_handle* h, double* out) {
+  GPE_TRY(finite(h, h->hres, 1, "an inner product"));
   *out = h->hres[0];
   return GPE_OK;
+}
+
+gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out) {
+  GPE_TRY(dot_enq(h, a, a32, b, b32, n));
+  GPE_TRY(fetch(h));
+  return dot_read(h, out);
+}
+
+gpe_status cg_enq(gpe_handle* h, double alpha, const void* p, const void* q, void* z, void* r) {
+  if (h->prec == GPE_MIXED) GPE_KT(h, KK_VECTOR, cg_update<float>(alpha, p, q, z, r, h->part, h->nblk, h->nel, h->st));
+  else GPE_KT(h, KK_VECTOR, cg_update<double>(alpha, p, q, z, r, h->part, h->nblk, h->nel, h->st));
+  return finalize_enq(h, 1, POST_NONE, nullptr);
 }
 
 // Interpolation matrix of the Fourier interpolant from n nodes to the 2n nodes
@@ -468,14 +538,17 @@ gpe_status gpe_destroy(gpe_handle* h) {
   if (!h) return GPE_OK;
   (void)hipSetDevice(h->device);
   if (h->st) (void)hipStreamSynchronize(h->st);
-  void* bufs[] = {h->ticket, h->V64, h->V32, h->part, h->res, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
+  if (!h->res_shared) {
+    if (h->res) (void)hipFree(h->res);
+    if (h->hres) (void)hipHostFree(h->hres);
+  }
+  void* bufs[] = {h->ticket, h->V64, h->V32, h->part, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
                   h->LX64, h->LX32,
                   h->tw[0], h->tw[1], h->tw[2], h->tw[3], h->tw[4], h->tw[5]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (void* b : h->solver_bufs)
     if (b) (void)hipFree(b);
-  if (h->hres) (void)hipHostFree(h->hres);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -562,7 +635,7 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     h->pstride = ps;
   }
   GPE_ALLOC(h->part, sizeof(double) * kMaxQ * h->pstride);
-  GPE_ALLOC(h->res, sizeof(double) * 64);
+  GPE_ALLOC(h->res, sizeof(double) * kResDoubles);
   GPE_ALLOC(h->gram_pt, sizeof(double) * 8);
   GPE_ALLOC(h->gram_tmp, sizeof(double) * 8);
   GPE_ALLOC(h->ticket, sizeof(unsigned int) * 4);
@@ -576,7 +649,7 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     GPE_ALLOC(h->T32, f32);
     GPE_ALLOC(h->Xp32, f32);
   }
-  if (hipHostMalloc((void**)&h->hres, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->hres, sizeof(double) * kResDoubles, hipHostMallocDefault) != hipSuccess) {
     g_create_error = "pinned host allocation failed";
     gpe_destroy(h);
     return GPE_ENOMEM;

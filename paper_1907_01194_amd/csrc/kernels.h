@@ -23,6 +23,11 @@ template <typename T>
 hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st);
 bool lap_size_supported(int n);
 
+// Partial sums per reduction slot (finalize).
+struct SlotCounts {
+  int nb[32];   // kMaxQ
+};
+
 // Physical constants of the pointwise terms, already combined with h:
 // zee[l] = b_l (storage order), c0 = 2 beta0 / h, ... (gradient factors)
 // and e0 = beta0 / (2h), ... (energy factors).
@@ -75,10 +80,9 @@ enum PostOp {
   // res = HVP slots 0..8 (x, y, z Parseval in 6, 7, 8), projection
   // coefficients in res[32..33] (zero for a Euclidean HVP):
   // writes kappa = <Z, HZ> to res[34] and ||Z||^2 to res[35].
-  POST_HVP_KAPPA = 3
-};
-struct SlotCounts {
-  int nb[32];   // kMaxQ
+  POST_HVP_KAPPA = 3,
+  // as POST_HVP_KAPPA for a Euclidean HVP: no projection, res[32..33] unused
+  POST_HVP_KAPPA_E = 4
 };
 // Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
 // (deterministic), then apply `post`.  ticket: a device counter that is 0
@@ -103,7 +107,8 @@ template <typename TU, typename TXI, typename TO>
 hipError_t scale_comps(int K, const void* u, const void* xi, double t, const double* s,
                        void* out, size_t npts, hipStream_t st);
 
-// y = a x + b y (complex fields of n elements of type T, real scalars).
+// y = a x + b y (complex fields of n elements of type T, real scalars);
+// b == 0 gives y = a x without reading y.
 template <typename T>
 hipError_t axpby(double a, const void* x, double b, void* y, size_t n, hipStream_t st);
 
@@ -123,6 +128,149 @@ hipError_t to_c128(const void* src, void* dst, size_t n, hipStream_t st);
 // out = a - b (complex fields) in T.
 template <typename TA, typename TB, typename TO>
 hipError_t diff(const void* a, const void* b, void* out, size_t n, hipStream_t st);
+
+// ---------------------------------------------------------------- batched launches
+// One launch runs an operation for nprob problems: problem p owns the
+// workgroups blk0[p] .. blk0[p+1]-1 (blk0: nprob + 1 non-decreasing ints in
+// device memory, blk0[0] = 0) and takes its arguments from args[p] (device
+// memory).  Within its range a problem's workgroups do exactly what a single
+// launch of that many workgroups does for it.
+struct Span {
+  const int* blk0;
+  int nprob;
+  int nblocks;   // blk0[nprob]
+};
+
+// Argument records of the elementwise and reduction operations above.
+// Reductions write partial sums part[q * nblk + wg] for their nblk
+// workgroups; elementwise operations take any workgroup count.
+template <typename T> struct AxpbyArgs {   // y = a x + b y; b == 0: y = a x (y not read)
+  const void* x;
+  void* y;
+  double a, b;
+  size_t n;
+};
+template <typename T> struct CgArgs {      // z += a p; r += a q; partials of ||r||^2
+  const void* p;
+  const void* q;
+  void* z;
+  void* r;
+  double* part;
+  double a;
+  size_t n;
+};
+template <typename TA, typename TB> struct DotArgs {   // partials of <a, b>
+  const void* a;
+  const void* b;
+  double* part;
+  size_t n;
+};
+template <typename TA, typename TB, typename TO> struct DiffArgs {   // out = a - b
+  const void* a;
+  const void* b;
+  void* out;
+  size_t n;
+};
+template <typename TI, typename TO> struct ConvArgs {   // dst = src (converted); src null: dst = 0
+  const void* src;
+  void* dst;
+  size_t n;
+};
+template <typename TU, typename TXI, typename TO> struct ScaleArgs {   // out_i = s_i (u_i + t xi_i)
+  const void* u;
+  const void* xi;
+  void* out;
+  double t;
+  double s[7];
+  size_t npts;
+  int K;
+};
+template <typename TU, typename TXI, int K> struct NormsArgs {   // retraction norms (see comp_norms)
+  const void* u;
+  const void* xi;
+  double* part;
+  size_t npts;
+};
+// out_i = W_i - (c0 + c1 l_i) X_i with (c0, c1) = coef[0..1] (device) or, if
+// coef is null, the values given; NORM: partials of ||out||^2.
+template <typename T, typename TX, bool NORM> struct ProjArgs {
+  const void* X;
+  const void* W;
+  void* out;
+  const double* coef;
+  double c0, c1;
+  double* part;
+  size_t npts;
+  int F;
+};
+template <typename T, int F, bool GRAD> struct PwGradArgs {   // see pw_grad
+  const void* X;
+  const void* LX;
+  const void* V;
+  void* G;
+  double* part;
+  size_t npts;
+  PwParams p;
+};
+
+// Single launch with nblk workgroups, and batched launch.
+template <typename A> hipError_t launch_single(const A& a, int nblk, hipStream_t st);
+template <typename A> hipError_t launch_batched(const A* args, const Span& sp, hipStream_t st);
+// Workgroups an elementwise operation over `total` elements uses.
+int elementwise_blocks(size_t total);
+
+// Batched finalize: problem p sums args[p].part (stride args[p].stride, counts
+// args[p].nb) into args[p].res with its own ticket and gram; grid (nq, nprob).
+struct FinArgs {
+  const double* part;
+  double* res;
+  double* gram;
+  unsigned int* ticket;
+  size_t stride;
+  SlotCounts nb;
+};
+hipError_t finalize_batched(const FinArgs* args, int nprob, int nq, int post, int F, hipStream_t st);
+
+// Batched axis pass (lap_axis_ex for every problem; line length n of each
+// problem's axis a power of two in 16..512, see batch_size_supported).
+template <typename T> struct LapArgs {
+  const void* in;
+  const void* acc;
+  void* out;
+  const void* tw;       // twiddles of that axis in precision T
+  const void* X;        // projection epilogue (null: none)
+  const double* coef;
+  double* part;         // Parseval partials (null: none)
+  double lamc;
+  long nlines;
+  size_t npts;
+  size_t stride;
+  int inner;
+  int n;
+};
+template <typename T>
+hipError_t lap_batched(const LapArgs<T>* args, const Span& sp, int F, int slot, hipStream_t st);
+int lap_batch_blocks(int n, long nlines);
+bool batch_size_supported(int n);
+
+// Batched fused x pass (hvp_xpass for every problem with schedule variant var).
+template <typename T> struct XpassArgs {
+  const void* X;
+  const void* Z;
+  const void* Y;
+  const void* V;
+  void* W;
+  const void* tw;
+  double* part;
+  double lamc;
+  size_t npts;
+  size_t stride;
+  int n;
+  PwParams p;
+};
+template <typename T>
+hipError_t xpass_batched(int F, int var, const XpassArgs<T>* args, const Span& sp, hipStream_t st);
+int xpass_batch_blocks(int n, int F, int var, size_t npts);
 
 // Multigrid transfer (c128 fields).  prolong_axis: out[o][j'][i] = scale *
 // sum_k P[j' n + k] in[o][k][i] with j' < 2n (P real, on the device).

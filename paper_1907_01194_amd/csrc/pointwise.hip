@@ -2,20 +2,25 @@
 // gradient), built on the spin algebra of spin.h.  The pointwise part of the
 // Hessian-vector product is fused into the x-axis Laplacian pass (lap.hip).
 #include "spin.h"
+#include "batch_ops.h"
 
 namespace gpe {
 
 template <typename T, int F, bool GRAD>
-__global__ void __launch_bounds__(kRedThreads)
-pw_grad_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ LX, const T* __restrict__ V,
-               c_t<T>* __restrict__ G, double* __restrict__ part, int nblk, size_t n, PwParams p) {
+__device__ void run_op(const PwGradArgs<T, F, GRAD>& a, int blk, int nblk) {
   using T2 = c_t<T>;
+  auto X = reinterpret_cast<const T2*>(a.X);
+  auto LX = reinterpret_cast<const T2*>(a.LX);
+  auto V = reinterpret_cast<const T*>(a.V);
+  auto G = reinterpret_cast<T2*>(a.G);
+  const size_t n = a.npts;
+  const PwParams& p = a.p;
   constexpr int K = 2 * F + 1;
   constexpr int NQ = 1 + 2 * K;
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (size_t)gridDim.x * blockDim.x) {
+  for (size_t j = (size_t)blk * blockDim.x + threadIdx.x; j < n; j += (size_t)nblk * blockDim.x) {
     T2 x[K], lx[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -60,33 +65,36 @@ pw_grad_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ LX, cons
       }
     }
   }
-  block_partials<NQ>(acc, part, nblk);
+  block_partials_any<NQ>(acc, a.part, nblk, blk);
 }
 
 template <typename T>
 hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, double* part, int nblk,
                    size_t npts, const PwParams& p, hipStream_t st) {
-  using T2 = c_t<T>;
-  auto x = reinterpret_cast<const T2*>(X);
-  auto lx = reinterpret_cast<const T2*>(LX);
-  auto g = reinterpret_cast<T2*>(G);
-#define GPE_LAUNCH(FF)                                                                              \
-  if (G)                                                                                            \
-    hipLaunchKernelGGL((pw_grad_kernel<T, FF, true>), dim3(nblk), dim3(kRedThreads), 0, st, x, lx, V, g, \
-                       part, nblk, npts, p);                                                        \
-  else                                                                                              \
-    hipLaunchKernelGGL((pw_grad_kernel<T, FF, false>), dim3(nblk), dim3(kRedThreads), 0, st, x, lx, V, g, \
-                       part, nblk, npts, p);
+#define GPE_LAUNCH(FF)                                                                             \
+  return G ? launch_single(PwGradArgs<T, FF, true>{X, LX, V, G, part, npts, p}, nblk, st)         \
+           : launch_single(PwGradArgs<T, FF, false>{X, LX, V, G, part, npts, p}, nblk, st);
   switch (F) {
-    case 1: GPE_LAUNCH(1) break;
-    case 2: GPE_LAUNCH(2) break;
-    case 3: GPE_LAUNCH(3) break;
+    case 1: GPE_LAUNCH(1)
+    case 2: GPE_LAUNCH(2)
+    case 3: GPE_LAUNCH(3)
     default: return hipErrorInvalidValue;
   }
 #undef GPE_LAUNCH
-  return hipGetLastError();
 }
 
+GPE_OP(PwGradArgs<double, 1, true>)
+GPE_OP(PwGradArgs<double, 2, true>)
+GPE_OP(PwGradArgs<double, 3, true>)
+GPE_OP(PwGradArgs<double, 1, false>)
+GPE_OP(PwGradArgs<double, 2, false>)
+GPE_OP(PwGradArgs<double, 3, false>)
+GPE_OP(PwGradArgs<float, 1, true>)
+GPE_OP(PwGradArgs<float, 2, true>)
+GPE_OP(PwGradArgs<float, 3, true>)
+GPE_OP(PwGradArgs<float, 1, false>)
+GPE_OP(PwGradArgs<float, 2, false>)
+GPE_OP(PwGradArgs<float, 3, false>)
 template hipError_t pw_grad<double>(int, const void*, const void*, const double*, void*, double*, int, size_t,
                                     const PwParams&, hipStream_t);
 template hipError_t pw_grad<float>(int, const void*, const void*, const float*, void*, double*, int, size_t,

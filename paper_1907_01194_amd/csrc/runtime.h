@@ -31,10 +31,11 @@ struct gpe_handle {
   void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   double* part = nullptr;      // kMaxQ slots of pstride (>= kMaxRedBlocks) partial sums
   size_t pstride = 0;
-  double* res = nullptr;       // 64 doubles
+  double* res = nullptr;       // kResDoubles doubles
   double* gram_pt = nullptr;   // ||u_i||^2 of the set point (7)
   double* gram_tmp = nullptr;  // scratch gram (7)
   double* hres = nullptr;      // pinned host mirror of res
+  bool res_shared = false;     // res / hres are slices of a batch's arrays (not owned)
   unsigned int* ticket = nullptr;  // finalize completion counter (0 between launches)
   int nblk = 1;
   int xvar = 1;                // schedule variant of the fused x pass (autotuned)
@@ -68,6 +69,8 @@ struct gpe_handle {
 };
 
 namespace gpe {
+
+constexpr int kResDoubles = 64;   // reduction results per handle (res, hres)
 
 // Status helpers: record a message on the handle and return the status.
 gpe_status fail(gpe_handle* h, gpe_status s, const std::string& msg);
@@ -117,16 +120,23 @@ gpe_status alloc_field(gpe_handle* h, void** p, size_t bytes);
 template <typename T>
 gpe_status laplacian(gpe_handle* h, const void* in, void* out);
 
-// Reduce the last launch's partials (nq values, plus post-op) and copy
-// res[0..nout) to h->hres (synchronises).
+// Operations that end in a reduction come in two halves: *_enq launches the
+// kernels and the finalize into h->res (stream-ordered, no synchronisation);
+// after h->res has reached h->hres (fetch, or a lock-step round of a batch)
+// *_read checks and returns the values.  The plain forms do both.
+gpe_status finalize_enq(gpe_handle* h, int nq, int post, double* gram);
+gpe_status fetch(gpe_handle* h);   // h->res -> h->hres, synchronises
 gpe_status reduce_to_host(gpe_handle* h, int nq, int post, double* gram, int nout);
 
 // Energy, gradient G (may be null), alpha_g/beta_g of G and ||X_i||^2 into gram.
-// Synchronises; fills *E, *ag, *bg.
+gpe_status eval_enq(gpe_handle* h, const void* X, void* G, double* gram);
+gpe_status eval_read(gpe_handle* h, bool grad, double* E, double* ag, double* bg);
 gpe_status eval_point(gpe_handle* h, const void* X, void* G, double* gram, double* E, double* ag,
                       double* bg);
 
 // gR = P_X G with the multipliers (ag, bg) already known; returns ||gR||.
+gpe_status pgrad_enq(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg);
+gpe_status pgrad_read(gpe_handle* h, double* gnorm);
 gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, double ag, double bg,
                         double* gnorm);
 
@@ -135,6 +145,9 @@ gpe_status adopt_point(gpe_handle* h);
 
 // HVP at the set point in the work precision; if kappa != null also
 // returns <Z, HZ> and ||Z||^2 (synchronises).
+PwParams hvp_params(const gpe_handle* h, bool riemannian, double sigma);
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma);
+gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz);
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, double* kappa,
                double* zz);
 
@@ -143,14 +156,24 @@ gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double s
 struct RetractNorms {
   double uu[7], ux[7], xx[7];
 };
+gpe_status norms_enq(gpe_handle* h, const void* u, const void* xi, bool xi32);
+gpe_status norms_read(gpe_handle* h, bool has_xi, RetractNorms* rn);
 gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32, RetractNorms* rn);
+// sigma_i of retraction `kind` at u + t xi, from the norms (host, FP64).
+gpe_status retract_sigma_at(gpe_handle* h, const RetractNorms& rn, double t, int kind, double* sig);
 gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32,
                          double t, int kind, void* out);
 // Scalar part of the retractions (host, FP64): sigma_i from component norms a_i.
 gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* sig);
 
 // <a, b> with a c128 and b in (b32 ? c64 : c128), or both in the work precision.
+gpe_status dot_enq(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n);
+gpe_status dot_read(gpe_handle* h, double* out);
 gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out);
+
+// CG step in the work precision: z += alpha p, r += alpha q, ||r||^2 into
+// res[0] (read with dot_read).
+gpe_status cg_enq(gpe_handle* h, double alpha, const void* p, const void* q, void* z, void* r);
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
 gpe_status tune_xpass(gpe_handle* h);

@@ -20,7 +20,8 @@
 //   * when the energy change and the model value are both below 16 eps |E|
 //     the trial is accepted (ratio 1) iff it lowers the Riemannian gradient
 //     norm; when |<grad, xi>| <= 16 eps |E| the Armijo search is skipped and
-//     the full step is tried; 12 rejections in a row end the run;
+//     the full step is tried, and if its energy change is resolved it is
+//     accepted iff the energy decreases; 12 rejections in a row end the run;
 //   * sigma_hat is kept >= sigma_hat_min (1e-8): a run of very successful
 //     steps would otherwise drive it to underflow, and the x10 increases on
 //     rejection could then never restore any regularisation.
@@ -37,7 +38,7 @@
 #include <vector>
 #include <string>
 
-#include "runtime.h"
+#include "sched.h"
 
 namespace gpe {
 
@@ -80,27 +81,170 @@ gpe_status ensure_bufs(gpe_handle* h) {
 
 }  // namespace
 
-static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
+// ---------------------------------------------------------------- requests
+// Builders of the queued operations (sched.h); a driver pushes them and
+// awaits a Round before reading results.
+namespace {
+
+Req rq_eval(const void* X, void* G, double* gram) {
+  Req r;
+  r.kind = RQ_EVAL;
+  r.a = X;
+  r.c = G;
+  r.gram = gram;
+  return r;
+}
+Req rq_pgrad(const void* X, const void* G, void* gR, double ag, double bg) {
+  Req r;
+  r.kind = RQ_PGRAD;
+  r.a = X;
+  r.b = G;
+  r.c = gR;
+  r.s0 = ag;
+  r.s1 = bg;
+  return r;
+}
+Req rq_norms(const void* u, const void* xi, bool xi32) {
+  Req r;
+  r.kind = RQ_NORMS;
+  r.a = u;
+  r.b = xi;
+  r.b32 = xi32;
+  return r;
+}
+Req rq_scale(const void* u, const void* xi, bool xi32, double t, const double* sig, void* out) {
+  Req r;
+  r.kind = RQ_SCALE;
+  r.a = u;
+  r.b = xi;
+  r.b32 = xi32;
+  r.c = out;
+  r.s0 = t;
+  for (int i = 0; i < 7; ++i) r.sig[i] = sig[i];
+  return r;
+}
+Req rq_dot(const void* a, bool a32, const void* b, bool b32, size_t n) {
+  Req r;
+  r.kind = RQ_DOT;
+  r.a = a;
+  r.a32 = a32;
+  r.b = b;
+  r.b32 = b32;
+  r.n = n;
+  return r;
+}
+Req rq_diff(const void* a, const void* b, void* out, bool out32, size_t n) {
+  Req r;
+  r.kind = RQ_DIFF;
+  r.a = a;
+  r.b = b;
+  r.c = out;
+  r.c32 = out32;
+  r.n = n;
+  return r;
+}
+Req rq_axpby(double a, const void* x, double b, void* y, bool w32, size_t n) {
+  Req r;
+  r.kind = RQ_AXPBY;
+  r.s0 = a;
+  r.a = x;
+  r.s1 = b;
+  r.c = y;
+  r.a32 = r.c32 = w32;
+  r.n = n;
+  return r;
+}
+Req rq_copy(const void* src, bool src32, void* dst, bool dst32, size_t n) {
+  Req r;
+  r.kind = RQ_COPY;
+  r.a = src;
+  r.a32 = src32;
+  r.c = dst;
+  r.c32 = dst32;
+  r.n = n;
+  return r;
+}
+Req rq_lap(const void* in, void* out, bool w32) {
+  Req r;
+  r.kind = RQ_LAP;
+  r.a = in;
+  r.c = out;
+  r.a32 = r.c32 = w32;
+  return r;
+}
+Req rq_hvp(const void* Z, void* HZ, bool riem, double sigma, bool w32) {
+  Req r;
+  r.kind = RQ_HVP;
+  r.a = Z;
+  r.c = HZ;
+  r.flag = riem;
+  r.s0 = sigma;
+  r.a32 = r.c32 = w32;
+  return r;
+}
+Req rq_cg(double alpha, const void* p, const void* q, void* z, void* res, bool w32) {
+  Req r;
+  r.kind = RQ_CG;
+  r.s0 = alpha;
+  r.a = p;
+  r.b = q;
+  r.c = z;
+  r.d = res;
+  r.a32 = r.c32 = w32;
+  return r;
+}
+
+// Make the handle's current point (Xp) the set point of its HVPs: the HVP
+// needs L X_p for <X_i, (LZ)_i> = <(LX)_i, Z_i>.
+void push_adopt(Ctx& c) {
+  gpe_handle* h = c.h;
+  if (h->prec == GPE_MIXED) {
+    c.push(rq_copy(h->Xp, false, h->Xp32, true, h->nel));
+    c.push(rq_lap(h->Xp32, h->LX32, true));
+  } else {
+    c.push(rq_lap(h->Xp, h->LX64, false));
+  }
+  h->has_point = true;
+}
+
+}  // namespace
+
+#define CO_TRY(call)                 \
+  do {                               \
+    gpe_status s_ = (call);          \
+    if (s_ != GPE_OK) co_return s_;  \
+  } while (0)
+#define ROUND co_await Round{}
+
+SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
+  gpe_handle* h = c.h;
   Clock clk;
-  GPE_TRY(ensure_bufs(h));
+  CO_TRY(ensure_bufs(h));
   auto& B = h->solver_bufs;
   const bool w32 = h->prec == GPE_MIXED;
   const size_t n = h->nel;
   const double eps = 2.220446049250313e-16;
-  hipStream_t s = h->st;
+  double sig[7];
 
   // u = psi(X0) (projective) into the set-point buffer
   {
     RetractNorms rn;
-    GPE_TRY(retract_norms(h, Xio, nullptr, false, &rn));
-    GPE_TRY(retract_apply(h, rn, Xio, nullptr, false, 0.0, GPE_R1_PROJECTIVE, h->Xp));
+    c.push(rq_norms(Xio, nullptr, false));
+    ROUND;
+    CO_TRY(norms_read(h, false, &rn));
+    CO_TRY(retract_sigma_at(h, rn, 0.0, GPE_R1_PROJECTIVE, sig));
+    c.push(rq_scale(Xio, nullptr, false, 0.0, sig, h->Xp));
   }
   void* u = h->Xp;
   void* G = h->Gp;
   void* gR = B[B_GR];
   double E, ag, bg, gn;
-  GPE_TRY(eval_point(h, u, G, h->gram_pt, &E, &ag, &bg));
-  GPE_TRY(project_grad(h, u, G, gR, ag, bg, &gn));
+  c.push(rq_eval(u, G, h->gram_pt));
+  ROUND;
+  CO_TRY(eval_read(h, true, &E, &ag, &bg));
+  c.push(rq_pgrad(u, G, gR, ag, bg));
+  ROUND;
+  CO_TRY(pgrad_read(h, &gn));
 
   // ------------------------------------------------------------ RGBB
   Clock crg;
@@ -110,22 +254,33 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
     for (int k = 0; k < o->rgbb_maxit && gn > o->rgbb_tol; ++k) {
       if (o->time_limit > 0 && clk.sec() > o->time_limit) break;
       RetractNorms rn;
-      GPE_TRY(retract_norms(h, u, gR, false, &rn));
+      c.push(rq_norms(u, gR, false));
+      ROUND;
+      CO_TRY(norms_read(h, true, &rn));
       double t = step, Ez = 0, agz = 0, bgz = 0;
       for (int ls = 0; ls < o->ls_max; ++ls) {
-        GPE_TRY(retract_apply(h, rn, u, gR, false, -t, o->retraction, B[B_Z]));
-        GPE_TRY(eval_point(h, B[B_Z], B[B_GZ], h->gram_tmp, &Ez, &agz, &bgz));
+        CO_TRY(retract_sigma_at(h, rn, -t, o->retraction, sig));
+        c.push(rq_scale(u, gR, false, -t, sig, B[B_Z]));
+        c.push(rq_eval(B[B_Z], B[B_GZ], h->gram_tmp));
+        ROUND;
+        CO_TRY(eval_read(h, true, &Ez, &agz, &bgz));
         st->ls_trials++;
         if (Ez <= C - o->rgbb_rho * t * gn * gn) break;
         t *= o->rgbb_delta;
       }
       double gnz;
-      GPE_TRY(project_grad(h, B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz, &gnz));
-      GPE_HIP(h, (diff<double, double, double>(B[B_Z], u, B[B_T1], n, s)));
-      GPE_HIP(h, (diff<double, double, double>(B[B_GRZ], gR, B[B_T2], n, s)));
+      c.push(rq_pgrad(B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz));
+      ROUND;
+      CO_TRY(pgrad_read(h, &gnz));
+      c.push(rq_diff(B[B_Z], u, B[B_T1], false, n));
+      c.push(rq_diff(B[B_GRZ], gR, B[B_T2], false, n));
+      c.push(rq_dot(B[B_T1], false, B[B_T2], false, n));
+      ROUND;
       double sv, vv;
-      GPE_TRY(dot_host(h, B[B_T1], false, B[B_T2], false, n, &sv));
-      GPE_TRY(dot_host(h, B[B_T2], false, B[B_T2], false, n, &vv));
+      CO_TRY(dot_read(h, &sv));
+      c.push(rq_dot(B[B_T2], false, B[B_T2], false, n));
+      ROUND;
+      CO_TRY(dot_read(h, &vv));
       if (vv > 0) step = std::fabs(sv) / vv;
       step = std::fmin(std::fmax(step, 1e-20), 1e20);
       const double Qn = o->rgbb_varrho * Q + 1.0;
@@ -153,19 +308,9 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
   h->E_pt = E;
   h->alpha_g = ag;
   h->beta_g = bg;
-  GPE_TRY(adopt_point(h));
+  push_adopt(c);
   double shat = o->sigma_hat0;
   int streak = 0;
-  auto to_work = [&](const void* src, void* dst) -> gpe_status {
-    if (w32) GPE_HIP(h, to_c64(src, dst, n, s));
-    else GPE_HIP(h, hipMemcpyAsync(dst, src, n * 16, hipMemcpyDeviceToDevice, s));
-    return GPE_OK;
-  };
-  auto axpby_w = [&](double a, const void* x, double b, void* y) -> gpe_status {
-    if (w32) GPE_HIP(h, axpby<float>(a, x, b, y, n, s));
-    else GPE_HIP(h, axpby<double>(a, x, b, y, n, s));
-    return GPE_OK;
-  };
   bool converged = false;
   for (int k = 0; k < o->maxit; ++k) {
     if (gn <= o->tol) {
@@ -182,13 +327,14 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
     void* Ap = B[B_AP];
     void* cz = B[B_CZ];
     void* xi = B[B_XI];
-    GPE_TRY(to_work(gR, B[B_GW]));
-    GPE_TRY(to_work(gR, r));
-    GPE_HIP(h, hipMemsetAsync(cz, 0, n * (w32 ? 8 : 16), s));
-    GPE_HIP(h, hipMemsetAsync(p, 0, n * (w32 ? 8 : 16), s));
-    GPE_TRY(axpby_w(-1.0, r, 0.0, p));
+    c.push(rq_copy(gR, false, B[B_GW], w32, n));
+    c.push(rq_copy(gR, false, r, w32, n));
+    c.push(rq_copy(nullptr, w32, cz, w32, n));
+    c.push(rq_axpby(-1.0, r, 0.0, p, w32, n));
+    c.push(rq_dot(r, w32, r, w32, n));
+    ROUND;
     double rr;
-    GPE_TRY(dot_host(h, r, w32, r, w32, n, &rr));
+    CO_TRY(dot_read(h, &rr));
     const double cg_tol = std::fmin(o->cg_T, std::pow(gn, o->cg_theta)) * gn;
     const double eps_c = 1e-12 * std::fmax(1.0, gn);
     bool have_d = false, s_is_mg = false;
@@ -196,7 +342,9 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
     int it = 0;
     for (; it < o->cg_maxit; ++it) {
       double kappa, pp;
-      GPE_TRY(hvp(h, p, Ap, true, sigma, &kappa, &pp));
+      c.push(rq_hvp(p, Ap, true, sigma, w32));
+      ROUND;
+      CO_TRY(hvp_read(h, &kappa, &pp));
       st->hvp_calls++;
       st->cg_total++;
       if (kappa <= eps_c * pp) {
@@ -209,43 +357,53 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
         break;
       }
       const double alpha = rr / kappa;
-      if (w32) GPE_HIP(h, cg_update<float>(alpha, p, Ap, cz, r, h->part, h->nblk, n, s));
-      else GPE_HIP(h, cg_update<double>(alpha, p, Ap, cz, r, h->part, h->nblk, n, s));
-      GPE_TRY(reduce_to_host(h, 1, POST_NONE, nullptr, 1));
-      const double rr_new = h->hres[0];
+      c.push(rq_cg(alpha, p, Ap, cz, r, w32));
+      ROUND;
+      double rr_new;
+      CO_TRY(dot_read(h, &rr_new));
       if (std::sqrt(rr_new) <= cg_tol) {
         ++it;
         break;
       }
-      GPE_TRY(axpby_w(-1.0, r, rr_new / rr, p));
+      c.push(rq_axpby(-1.0, r, rr_new / rr, p, w32, n));
       rr = rr_new;
     }
     // ---- direction xi = s + tau d (eq. xi)
-    if (s_is_mg) GPE_TRY(axpby_w(-1.0, B[B_GW], 0.0, xi));
-    else GPE_HIP(h, hipMemcpyAsync(xi, cz, n * (w32 ? 8 : 16), hipMemcpyDeviceToDevice, s));
+    if (s_is_mg) c.push(rq_axpby(-1.0, B[B_GW], 0.0, xi, w32, n));
+    else c.push(rq_copy(cz, w32, xi, w32, n));
     if (have_d) {
       double dg;
-      GPE_TRY(dot_host(h, p, w32, B[B_GW], w32, n, &dg));
-      GPE_TRY(axpby_w(dg / kappa_d, p, 1.0, xi));
+      c.push(rq_dot(p, w32, B[B_GW], w32, n));
+      ROUND;
+      CO_TRY(dot_read(h, &dg));
+      c.push(rq_axpby(dg / kappa_d, p, 1.0, xi, w32, n));
     }
     double slope;
-    GPE_TRY(dot_host(h, gR, false, xi, w32, n, &slope));
+    c.push(rq_dot(gR, false, xi, w32, n));
+    ROUND;
+    CO_TRY(dot_read(h, &slope));
 
     // ---- Armijo curvilinear search on the model (eq. tp1, tp2).  Near FP64
     // resolution (|<grad, xi>| <= 16 eps |E|) model values are rounding noise:
     // the full step is tried and the gradient norm decides below.
     RetractNorms rn;
-    GPE_TRY(retract_norms(h, u, xi, w32, &rn));
+    c.push(rq_norms(u, xi, w32));
+    ROUND;
+    CO_TRY(norms_read(h, true, &rn));
     const bool resolved = std::fabs(slope) > 16 * eps * std::fabs(E);
     double t = o->alpha0, m = 0;
     bool ok = false;
     for (int ls = 0; resolved && ls < o->ls_max; ++ls) {
-      GPE_TRY(retract_apply(h, rn, u, xi, w32, t, o->retraction, B[B_Z]));
-      if (w32) GPE_HIP(h, (diff<double, double, float>(B[B_Z], u, B[B_DZ], n, s)));
-      else GPE_HIP(h, (diff<double, double, double>(B[B_Z], u, B[B_DZ], n, s)));
+      CO_TRY(retract_sigma_at(h, rn, t, o->retraction, sig));
+      c.push(rq_scale(u, xi, w32, t, sig, B[B_Z]));
+      c.push(rq_diff(B[B_Z], u, B[B_DZ], w32, n));
+      c.push(rq_hvp(B[B_DZ], B[B_HDZ], false, 0.0, w32));
+      ROUND;
       double dHd, dd, gd;
-      GPE_TRY(hvp(h, B[B_DZ], B[B_HDZ], false, 0.0, &dHd, &dd));
-      GPE_TRY(dot_host(h, G, false, B[B_DZ], w32, n, &gd));
+      CO_TRY(hvp_read(h, &dHd, &dd));
+      c.push(rq_dot(G, false, B[B_DZ], w32, n));
+      ROUND;
+      CO_TRY(dot_read(h, &gd));
       m = gd + 0.5 * dHd + 0.5 * sigma * dd;
       st->hvp_calls++;
       st->ls_trials++;
@@ -256,18 +414,25 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
       t *= o->delta;
     }
     if (!resolved) {
-      GPE_TRY(retract_apply(h, rn, u, xi, w32, t, o->retraction, B[B_Z]));
+      CO_TRY(retract_sigma_at(h, rn, t, o->retraction, sig));
+      c.push(rq_scale(u, xi, w32, t, sig, B[B_Z]));
       ok = true;
       m = 0.0;
     }
     double ratio = -INFINITY, Ez = 0, agz = 0, bgz = 0, gnz = -1.0;
     if (ok) {
-      GPE_TRY(eval_point(h, B[B_Z], B[B_GZ], h->gram_tmp, &Ez, &agz, &bgz));
+      c.push(rq_eval(B[B_Z], B[B_GZ], h->gram_tmp));
+      ROUND;
+      CO_TRY(eval_read(h, true, &Ez, &agz, &bgz));
       const double dE = Ez - E;
       if (std::fabs(dE) <= 16 * eps * std::fabs(E) && std::fabs(m) <= 16 * eps * std::fabs(E)) {
         // energies cannot rank u and z: the Riemannian gradient norm does
-        GPE_TRY(project_grad(h, B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz, &gnz));
+        c.push(rq_pgrad(B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz));
+        ROUND;
+        CO_TRY(pgrad_read(h, &gnz));
         ratio = gnz < gn ? 1.0 : -INFINITY;
+      } else if (!resolved) {
+        ratio = dE < 0 ? 1.0 : -INFINITY;   // the model was not evaluated: the energy decides
       } else {
         ratio = dE / m;
       }
@@ -285,11 +450,13 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
       E = Ez;
       ag = agz;
       bg = bgz;
-      GPE_TRY(project_grad(h, u, G, gR, ag, bg, &gn));
+      c.push(rq_pgrad(u, G, gR, ag, bg));
+      ROUND;
+      CO_TRY(pgrad_read(h, &gn));
       h->E_pt = E;
       h->alpha_g = ag;
       h->beta_g = bg;
-      GPE_TRY(adopt_point(h));
+      push_adopt(c);
       shat = std::fmax(shat * (ratio >= o->eta2 ? o->gamma0 : o->gamma1), o->sigma_hat_min);
       streak = 0;
     } else {
@@ -301,18 +468,28 @@ static gpe_status newton_solve_one(gpe_handle* h, void* Xio, const gpe_solve_opt
   }
   st->t_arnt = carnt.sec();
 
-  GPE_HIP(h, hipMemcpyAsync(Xio, u, n * 16, hipMemcpyDeviceToDevice, s));
-  double mass, mag;
-  GPE_TRY(gpe_constraints(h, u, &mass, &mag));
+  c.push(rq_copy(u, false, Xio, false, n));
+  c.push(rq_norms(u, nullptr, false));
+  ROUND;
+  RetractNorms fin;
+  CO_TRY(norms_read(h, false, &fin));
+  double mass = 0, mag = 0;
+  for (int i = 0; i < h->K; ++i) {
+    mass += fin.uu[i];
+    mag += (h->F - i) * fin.uu[i];
+  }
   st->E = E;
   st->gnorm = gn;
   st->converged = converged;
   st->mass_err = std::fabs(mass - 1.0);
   st->mag_err = std::fabs(mag - h->M);
   st->t_total = clk.sec();
-  if (!converged) return fail(h, GPE_ENOTCONV, "tolerance not reached");
-  return GPE_OK;
+  if (!converged) co_return fail(h, GPE_ENOTCONV, "tolerance not reached");
+  co_return GPE_OK;
 }
+
+#undef CO_TRY
+#undef ROUND
 
 // Cascadic multigrid (Algorithm 1, outer loop): solve on the coarsest of
 // mg_levels nested meshes (every axis halved per level, same box, V and the
@@ -331,7 +508,7 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
       }
     }
   if (L <= 0) {
-    gpe_status r = newton_solve_one(h, Xio, o, st);
+    gpe_status r = solve_single(h, Xio, o, st);
     st->mg_levels = 0;
     return r;
   }
@@ -376,7 +553,7 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
     if (o->time_limit > 0) oc.time_limit = std::fmax(o->time_limit - clk.sec(), 1e-3);
     gpe_solve_stats sc;
     std::memset(&sc, 0, sizeof(sc));
-    gpe_status r = newton_solve_one(hs[l], xs[l], &oc, &sc);
+    gpe_status r = solve_single(hs[l], xs[l], &oc, &sc);
     if (r != GPE_OK && r != GPE_ENOTCONV) {
       rs = fail(h, r, std::string("multigrid: coarse solve: ") + hs[l]->err);
       break;
@@ -396,7 +573,7 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
   gpe_solve_opts of = *o;
   of.mg_levels = 0;
   if (o->time_limit > 0) of.time_limit = std::fmax(o->time_limit - clk.sec(), 1e-3);
-  gpe_status r = newton_solve_one(h, Xio, &of, st);   // counters: finest mesh only
+  gpe_status r = solve_single(h, Xio, &of, st);   // counters: finest mesh only
   st->mg_levels = L;
   st->t_coarse = t_coarse;
   st->t_total += t_coarse;

@@ -118,6 +118,22 @@ def spin2_3d(n=96):
                      harmonic((1.0, 1.0, 1.0)), (100, 1, -1), 0.3)
 
 
+def spin1_2d_batch(count=64, seed=5, sizes=(64, 128, 256)):
+    """Batched workload: `count` spin-1 2D problems, n x n with n drawn from
+    `sizes`, on spin2_2d's box and potential ([-12,12]^2, |x|^2/2 + 10 sum
+    sin^2(pi x_a/4)), beta = (100, beta1) with beta1 ~ U[-1, 1] and M ~
+    U[0, 0.9] (seeded)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.choice(np.asarray(sizes)))
+        b1 = float(rng.uniform(-1.0, 1.0))
+        M = float(rng.uniform(0.0, 0.9))
+        specs.append(make_spec("spin1-2d-%d-b%d" % (n, i), 1, (n, n), (-12, -12), (12, 12),
+                               lattice(10.0, np.pi / 4), (100, b1), M))
+    return specs
+
+
 # ---------------------------------------------------------------- inputs
 
 def cn(rng, shape):

@@ -1,0 +1,128 @@
+"""Batched form: many spin-1 2D problems of uneven grids and parameters run
+in lock step through gpe_batch_* (one launch per kernel stage for all of
+them).  Parity: the batched HVP against the single-problem HVP and the
+oracle's Riemannian Hessian, the batched Newton solve against the oracle's
+energies (FP64: 1e-10 relative, mixed: 1e-5) and against the same problems
+solved one at a time."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_01194_amd import workloads as W
+from helpers import oracle_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _points(batch, specs, seed0):
+    """Set points psi(X0) (C1's initial recipe) and unit tangent directions."""
+    from gpu_util import dev
+    pts, dirs = [], []
+    for i, (p, sp) in enumerate(zip(batch.problems, specs)):
+        X = p.retract(dev(W.initial_state(sp, seed0 + i)), None)
+        D = p.project(X, dev(W.random_direction(sp, 100 + seed0 + i)))
+        D = D / float(D.abs().pow(2).sum().sqrt())
+        pts.append(X)
+        dirs.append(D)
+    return pts, dirs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_hvp_matches_single_and_oracle(torch, precision):
+    from paper_1907_01194_amd.binding import Batch
+    from gpu_util import host
+    specs = W.spin1_2d_batch(count=7, seed=11, sizes=(16, 32, 64))
+    print("batch hvp", precision, [s.n for s in specs], flush=True)
+    b = Batch(specs, precision)
+    pts, dirs = _points(b, specs, 40)
+    wd = b.problems[0].work_dtype
+    Z = [d.to(wd) for d in dirs]
+    sig = [1e-2 * (i + 1) for i in range(len(specs))]
+    for p, X in zip(b.problems, pts):
+        p.set_point(X)
+    for riem in (True, False):
+        HB, kap = b.hvp(Z, riemannian=riem, sigma=sig)
+        torch.cuda.synchronize()
+        for i, (p, sp) in enumerate(zip(b.problems, specs)):
+            HS = p.hvp(Z[i], riemannian=riem, sigma=sig[i])
+            tol_s = 1e-12 if precision == "fp64" else 2e-6
+            assert rel(host(HB[i]), host(HS)) <= tol_s, (i, riem)
+            op = oracle_problem(sp)
+            u, z = host(pts[i]), host(Z[i])
+            ref = oracle.rhess(op, u, z, sig[i]) if riem else oracle.hvp(op, u, z)
+            tol_o = 1e-10 if precision == "fp64" else 1e-5
+            assert rel(host(HB[i]), ref) <= tol_o, (i, riem)
+            k_ref = float(np.real(np.vdot(z, ref)))
+            assert abs(kap[i] - k_ref) <= tol_o * max(abs(k_ref), 1.0), (i, riem)
+    b.close()
+
+
+def _pick(pairs, sizes=(16, 32, 64)):
+    """Problems (and their initial-state seeds) picked from seeded batches:
+    pairs of (batch seed, index).  The picks are ones whose oracle solve takes
+    seconds, not minutes (problems with soft modes need thousands of HVPs)."""
+    specs, seeds = [], []
+    for seed, i in pairs:
+        specs.append(W.spin1_2d_batch(count=6, seed=seed, sizes=sizes)[i])
+        seeds.append(60 + i)
+    return specs, seeds
+
+
+def test_batch_solve_fp64_matches_oracle_and_single(torch):
+    from paper_1907_01194_amd.binding import Batch, Problem
+    from gpu_util import dev
+    specs, seeds = _pick([(8, 1), (8, 2), (8, 3), (8, 5), (0, 0)])
+    print("batch solve fp64", [(s.n, s.beta[1], s.M) for s in specs], flush=True)
+    X0 = [W.initial_state(sp, sd) for sp, sd in zip(specs, seeds)]
+    b = Batch(specs, "fp64")
+    Xs, stats = b.newton_solve([dev(x) for x in X0], tol=1e-8)
+    for i, sp in enumerate(specs):
+        st = stats[i]
+        assert st["converged"], (i, st)
+        assert st["gnorm"] <= 1e-8
+        assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+        _, so = oracle.solve(oracle_problem(sp), X0[i], oracle.SolveOpts(tol=1e-8))
+        assert so.converged
+        assert abs(st["E"] - so.E) <= 1e-10 * abs(so.E), (i, st["E"], so.E)
+        ps = Problem(sp, "fp64")
+        _, s1 = ps.newton_solve(dev(X0[i]), tol=1e-8)
+        assert abs(st["E"] - s1["E"]) <= 1e-12 * abs(s1["E"])
+        ps.close()
+    b.close()
+
+
+def test_batch_solve_mixed_uneven_grids(torch):
+    from paper_1907_01194_amd.binding import Batch
+    from gpu_util import dev
+    specs, seeds = _pick([(5, 1), (5, 2), (5, 3), (5, 4), (8, 3)])
+    print("batch solve mixed", [(s.n, s.beta[1], s.M) for s in specs], flush=True)
+    X0 = [W.initial_state(sp, sd) for sp, sd in zip(specs, seeds)]
+    b = Batch(specs, "mixed")
+    v, us = b.schedule()
+    assert 0 <= v < 3 and us[v] > 0
+    Xs, stats = b.newton_solve([dev(x) for x in X0], tol=1e-6)
+    for i, sp in enumerate(specs):
+        st = stats[i]
+        assert st["converged"], (i, st)
+        assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+        _, so = oracle.solve(oracle_problem(sp), X0[i], oracle.SolveOpts(tol=1e-6))
+        assert abs(st["E"] - so.E) <= 1e-5 * abs(so.E), (i, st["E"], so.E)
+    b.close()
+
+
+def test_batch_rejects_unsupported(torch):
+    from paper_1907_01194_amd.binding import Batch, GpeError
+    specs = W.spin1_2d_batch(count=2, seed=1, sizes=(16,))
+    bad = W.make_spec("odd", 1, (24, 24), (-12, -12), (12, 12), W.lattice(10.0, np.pi / 4), (100, 0.5), 0.3)
+    with pytest.raises(GpeError):
+        Batch(specs + [bad], "mixed")
+    other = W.spin2_2d()
+    with pytest.raises(GpeError):
+        Batch(specs + [other], "mixed")
