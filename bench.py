@@ -14,7 +14,13 @@ rooflines, time-to-ground-state for both precisions (full newton_solve:
 retraction, RGBB, ARNT, energies and gradients) and the CPU oracle timing
 ride on the same JSON line.
 
+The batched form (64 spin-1 2D problems of uneven grids in one gpe_batch:
+one batched HVP pass against the same HVPs one by one, and with
+--batch-solve the lock-step Newton solve against one-by-one solves) rides on
+the same line under "batched".
+
     python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-solve] [--no-cpu]
+                    [--no-batch] [--batch-solve]
 """
 
 import argparse
@@ -56,6 +62,10 @@ def parse():
     ap.add_argument("--solve-time", type=float, default=45.0,
                     help="wall-clock cap per solve of the benchmark physics (s)")
     ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-HVP measurement")
+    ap.add_argument("--batch-solve", action="store_true",
+                    help="also time the lock-step batched solve of the 64 problems against one-by-one solves")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -176,6 +186,99 @@ def time_solve(spec, prec, w, limit, log):
             "hvp_calls": st["hvp_calls"], "t_rgbb": round(st["t_rgbb"], 3), "t_arnt": round(st["t_arnt"], 3)}
 
 
+def batch_measure(count, steps, solve, log):
+    """Batched form: `count` spin-1 2D problems of uneven grids (64^2, 128^2,
+    256^2) and parameters in one gpe_batch.  Times one batched Riemannian HVP
+    pass over all problems (one launch per kernel stage) against the same HVPs
+    issued problem by problem, and optionally the lock-step Newton solve of
+    all problems against solving them one at a time."""
+    import torch
+    from paper_1907_01194_amd import workloads as W
+    from paper_1907_01194_amd.binding import Batch, Problem
+    specs = W.spin1_2d_batch(count=count, seed=5)
+    t0 = time.perf_counter()
+    b = Batch(specs, "mixed")
+    t_create = time.perf_counter() - t0
+    sched = b.schedule()
+    X0 = [torch.from_numpy(W.initial_state(sp, 60 + i)).cuda() for i, sp in enumerate(specs)]
+    Z = []
+    for i, (p, sp) in enumerate(zip(b.problems, specs)):
+        u = p.retract(X0[i], None)
+        d = p.project(u, torch.from_numpy(W.random_direction(sp, 200 + i)).cuda())
+        d /= float(d.abs().pow(2).sum().sqrt())
+        p.set_point(u)
+        Z.append(d.to(p.work_dtype).contiguous())
+    sig = [1e-2] * count
+    HZ = [p.empty(work=True) for p in b.problems]
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        b.hvp(Z, True, sig, HZ)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        b.hvp(Z, True, sig, HZ)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / steps
+    for p, z, h in zip(b.problems, Z, HZ):
+        p.hvp_dot(z, 1e-2, out=h)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        for p, z, h in zip(b.problems, Z, HZ):
+            p.hvp_dot(z, 1e-2, out=h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / steps
+    pts = sum(int(np.prod(sp.n)) for sp in specs)
+    sizes = {}
+    for sp in specs:
+        sizes[sp.n[0]] = sizes.get(sp.n[0], 0) + 1
+    log("batch of %d (%s): %.1f us per batched HVP pass, %.1f us one by one; x-pass variant %d %s" % (
+        count, sizes, 1e3 * batched_ms, 1e3 * seq_ms, sched[0], sched[1]))
+    out = {"workload": "%d spin-1 2D problems, n^2 with n in {64,128,256}, [-12,12]^2, lattice V, "
+                       "beta=(100, U[-1,1]), M=U[0,0.9], seed 5" % count,
+           "grid_counts": {str(k): v for k, v in sorted(sizes.items())}, "grid_points": pts,
+           "precision": "mixed", "create_s": round(t_create, 3),
+           "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]},
+           "batched_pass_us": round(1e3 * batched_ms, 2), "sequential_pass_us": round(1e3 * seq_ms, 2),
+           "hvp_per_s_batched": round(count / (batched_ms / 1e3), 1),
+           "hvp_per_s_sequential": round(count / (seq_ms / 1e3), 1),
+           "speedup": round(seq_ms / batched_ms, 2)}
+    if solve:
+        Xb = [x.clone() for x in X0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = b.newton_solve(Xb, check=False, tol=1e-6)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        conv = sum(int(s["converged"]) for s in st)
+        log("batched solve: %.2f s, %d/%d converged, max hvp %d" % (tb, conv, count, max(s["hvp_calls"] for s in st)))
+        ts, E1 = 0.0, []
+        for i, sp in enumerate(specs):
+            p = Problem(sp, "mixed")
+            x = X0[i].clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, s1 = p.newton_solve(x, check=False, tol=1e-6)
+            torch.cuda.synchronize()
+            ts += time.perf_counter() - t0
+            E1.append(s1["E"])
+            p.close()
+        dE = max(abs(a["E"] - e) / abs(e) for a, e in zip(st, E1))
+        log("one-by-one solves: %.2f s; max relative energy difference %.2e" % (ts, dE))
+        out["solve"] = {"tol": 1e-6, "batched_s": round(tb, 3), "sequential_s": round(ts, 3),
+                        "speedup": round(ts / tb, 2), "converged": conv,
+                        "max_hvp_calls": max(s["hvp_calls"] for s in st),
+                        "total_hvp_calls": sum(s["hvp_calls"] for s in st),
+                        "max_rel_energy_diff_vs_sequential": dE}
+    b.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(spec, w, noise, log):
     """The oracle (FP64, NumPy/scipy) per Riemannian HVP on the same workload."""
     here = os.path.dirname(os.path.abspath(__file__))
@@ -248,6 +351,7 @@ def main():
         for prec in precs:
             entry[prec] = time_solve(spec, prec, bw, args.solve_time, log)
         solves["benchmark_physics"] = entry
+    batch = None if args.no_batch else batch_measure(args.batch_count, 50, args.batch_solve, log)
     cpu = None if args.no_cpu else cpu_baseline(spec, w, noise, log)
     head = precs[0]
     out = {
@@ -273,6 +377,7 @@ def main():
                            "roofline": r["roofline"], "kernels_us": r["kernels_us"],
                            "xpass_schedule": r["xpass_schedule"]} for p, r in res.items()},
         "time_to_ground_state": solves or None,
+        "batched": batch,
     }
     print(json.dumps(out), flush=True)
 
