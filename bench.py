@@ -33,12 +33,17 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
-# HBM bytes per launch of the dominant HVP kernel from the FETCH_SIZE / WRITE_SIZE
-# rocprofv3 runs recorded in profiles/hvp_spin3_128_hbm_counters.md (copy-kernel
-# calibrated); valid only while the kernel sources hash to `src_hash`.
-MEASURED_TRAFFIC = {
-    "src_hash": "44afa8319c279d46",
-    "hvp_xpass": {"mixed": 482981775, "fp64": 1127698898},
+# VALU lane-operation peak of MI355X without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the published 78.6 TFLOP/s FP64 / non-packed FP32 vector rate, an FMA counting as 2 flops).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Per-launch counters of the dominant HVP kernel from rocprofv3 runs recorded in
+# profiles/hvp_spin3_128_*.md: HBM bytes (FETCH_SIZE / WRITE_SIZE, copy-kernel
+# calibrated) and VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes),
+# by schedule variant; valid only while the kernel sources hash to `src_hash`.
+MEASURED = {
+    "src_hash": "",
+    "hvp_xpass": {"traffic": {}, "valu": {}},
 }
 
 
@@ -46,7 +51,7 @@ def kernel_src_hash():
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1907_01194_amd", "csrc")
-    for f in ("lap.hip", "spin.h", "common.h"):
+    for f in ("lap.hip", "fft.h", "spin.h", "common.h"):
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -138,7 +143,11 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log):
     return ms, kt, sched
 
 
-def roofline(spec, prec, ms, kt):
+def roofline(spec, prec, ms, kt, variant):
+    """Roofline of the dominant kernel and of the whole HVP.  The fused x pass
+    is VALU-bound when its counters are on record (its VALU lane-operation rate
+    against VALU_PEAK_TOPS is then the headline fraction; its HBM rate rides
+    along), else it is reported against HBM."""
     K = spec.K
     npts = int(np.prod(spec.n))
     cb, rb = (16, 8) if prec == "fp64" else (8, 4)
@@ -151,13 +160,25 @@ def roofline(spec, prec, ms, kt):
     achieved = b / per_launch_s / 1e9
     hvp_bytes = 3 * K * npts * cb + npts * rb             # read X, Z, V; write HZ
     hvp_gbs = hvp_bytes / (ms / 1e3) / 1e9
-    traffic = None
-    if npts == 128 ** 3 and kernel_src_hash() == MEASURED_TRAFFIC["src_hash"]:
-        traffic = MEASURED_TRAFFIC.get(dom, {}).get(prec)
+    traffic = valu = None
+    if npts == 128 ** 3 and K == 7 and kernel_src_hash() == MEASURED["src_hash"]:
+        rec = MEASURED.get(dom, {})
+        traffic = rec.get("traffic", {}).get(prec, {}).get(str(variant))
+        valu = rec.get("valu", {}).get(prec, {}).get(str(variant))
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    if valu:
+        ops = valu * 64
+        tops = ops / per_launch_s / 1e12
+        kern = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s (VALU lane operations)", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                "traffic": traffic, "valu_lane_ops_per_launch": ops, "hbm": hbm}
+    else:
+        kern = dict(hbm)
+    kern.update({"name": dom, "schedule_variant": variant, "bytes_per_launch": b,
+                 "us_per_launch": round(per_launch_s * 1e6, 2)})
     return {
-        "kernel": {"bound": "hbm", "name": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                   "bytes_per_launch": b, "us_per_launch": round(per_launch_s * 1e6, 2)},
+        "kernel": kern,
         "hvp": {"bound": "hbm", "achieved": round(hvp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hvp_gbs / HBM_PEAK_GBS, 4), "compulsory_bytes": hvp_bytes,
                 "us_per_hvp": round(ms * 1e3, 2)},
@@ -326,7 +347,7 @@ def main():
     res = {}
     for prec in precs:
         ms, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
-        res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "roofline": roofline(spec, prec, ms, kt),
+        res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "roofline": roofline(spec, prec, ms, kt, sched[0]),
                      "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()},
                      "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]}}
     solves = {}

@@ -359,32 +359,34 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
 #pragma unroll
   for (int i = 0; i < K; ++i) zcoef[i] = (T)p.zc[i];
   double acc[7] = {0, 0, 0, 0, 0, 0, pars};
+  // Per point the partial sums run over the K components in the work
+  // precision; the sums over points accumulate in FP64.
   auto point = [&](int rr, int xx) {
-    double xy = 0, lxy = 0;
+    T s_xw = 0, s_lxw = 0, s_xz = 0, s_lxz = 0, s_zq = 0, s_zz = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const double c = (double)cdotr(y[i], z[i]);     // <(LX)_i, Z_i> = <X_i, (LZ)_i>
-      xy += c;
-      lxy += (double)(F - i) * c;
+      const T c = cdotr(y[i], z[i]);     // <(LX)_i, Z_i> = <X_i, (LZ)_i>
+      const T xz = cdotr(x[i], z[i]);
+      s_xw += c;
+      s_lxw += T(F - i) * c;
+      s_xz += xz;
+      s_lxz += T(F - i) * xz;
+      s_zz += cabs2(z[i]);
     }
-    T2 q[K];
-    hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) { q[i] = qi; });
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
+    hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) {
       const T2 lz = lds[(i * RPB + rr) * (N + 1) + xx];
-      W[i * npts + j] = cadd(lz, q[i]);
-      const double xq = (double)cdotr(x[i], q[i]);
-      const double xz = (double)cdotr(x[i], z[i]);
-      const double l = (double)(F - i);
-      xy += xq;
-      lxy += l * xq;
-      acc[2] += xz;
-      acc[3] += l * xz;
-      acc[4] += (double)cdotr(z[i], q[i]);
-      acc[5] += (double)cabs2(z[i]);
-    }
-    acc[0] += xy;
-    acc[1] += lxy;
+      W[i * npts + j] = cadd(lz, qi);
+      const T xq = cdotr(x[i], qi);
+      s_xw += xq;
+      s_lxw += T(F - i) * xq;
+      s_zq += cdotr(z[i], qi);
+    });
+    acc[0] += (double)s_xw;
+    acc[1] += (double)s_lxw;
+    acc[2] += (double)s_xz;
+    acc[3] += (double)s_lxz;
+    acc[4] += (double)s_zq;
+    acc[5] += (double)s_zz;
   };
   if constexpr (kPrefetch) {
     while (have) {

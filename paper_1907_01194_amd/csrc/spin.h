@@ -13,6 +13,8 @@
 // A_{+-2} exactly as printed in Sec. 2 (A_0 centre entry sqrt(2/3)/sqrt(7)).
 // Storage index i holds l_i = F - i.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -123,68 +125,131 @@ __device__ __forceinline__ c_t<T> ffy(T fz, c_t<T> fp, const c_t<T> (&y)[2 * F +
 }
 
 
+// Compile-time loop: fn(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, typename Fn> __device__ __forceinline__ void sfor(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(fn);
+  }
+}
+
+// acc += s conj(a) b and acc += s a b for real s (FMA-shaped).
+template <typename T2, typename S> __device__ __forceinline__ void acc_cjmul(T2& acc, T2 a, T2 b, S s) {
+  acc.x += s * (a.x * b.x + a.y * b.y);
+  acc.y += s * (a.x * b.y - a.y * b.x);
+}
+template <typename T2, typename S> __device__ __forceinline__ void acc_mul(T2& acc, T2 a, T2 b, S s) {
+  acc.x += s * (a.x * b.x - a.y * b.y);
+  acc.y += s * (a.x * b.y + a.y * b.x);
+}
+// s (a b + c d)
+template <typename T2, typename S> __device__ __forceinline__ void acc_mul2(T2& acc, T2 a, T2 b, T2 c, T2 d, S s) {
+  acc.x += s * ((a.x * b.x - a.y * b.y) + (c.x * d.x - c.y * d.y));
+  acc.y += s * ((a.x * b.y + a.y * b.x) + (c.x * d.y + c.y * d.x));
+}
+// s (conj(a) b + conj(c) d)
+template <typename T2, typename S> __device__ __forceinline__ void acc_cjmul2(T2& acc, T2 a, T2 b, T2 c, T2 d, S s) {
+  acc.x += s * ((a.x * b.x + a.y * b.y) + (c.x * d.x + c.y * d.y));
+  acc.y += s * ((a.x * b.y - a.y * b.x) + (c.x * d.y - c.y * d.x));
+}
+
 // Pointwise Hessian terms of the Sec. 3 HVP formula at one point, for all
 // components: q_i = 2 (V + b_i) Z_i + zc_i Z_i + (2/h)[beta0 ... + beta3 ...]
 // (the Laplacian term is added by the caller); sink(i, q_i) receives each.
+//
+// Written for few operations: the densities of X and their derivatives along
+// Z are scaled once by their coupling constants; the pair amplitudes use the
+// symmetry of the singlet vector and of the matrices A_m (entry (i, k) equals
+// entry (k, i), so each unordered pair is formed once), and zero matrix
+// entries are skipped at compile time.  The algebra is the formula's own.
 template <typename T, int F, typename Sink>
 __device__ __forceinline__ void hvp_point(const c_t<T> (&x)[2 * F + 1], const c_t<T> (&z)[2 * F + 1], T v,
                                           const PwParams& p, const T (&zcoef)[2 * F + 1], Sink&& sink) {
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
-  Dens<T, F> d;
-  densities<T, F>(x, d);
-  T drho = 0, dfz = 0;
+  // rho, F_z and their derivatives d rho = 2 Re sum Z conj X, d F_z likewise
+  T rho = 0, fz = 0, drho = 0, dfz = 0;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const T r = cdotr(z[i], x[i]);
+    const T a = x[i].x * x[i].x + x[i].y * x[i].y;
+    const T r = z[i].x * x[i].x + z[i].y * x[i].y;
+    rho += a;
+    fz += T(F - i) * a;
     drho += r;
     dfz += T(F - i) * r;
   }
-  drho *= T(2);
-  dfz *= T(2);
-  T2 dfp = mk<T2>(0, 0);
-#pragma unroll
-  for (int i = 1; i < K; ++i)
-    dfp = cadd(dfp, cscale(cadd(cmulc(z[i - 1], x[i]), cmulc(x[i - 1], z[i])), (T)raise_c<F>(i)));
-  T2 da00 = mk<T2>(0, 0);
+  // F_+ = sum cr_i conj(X_{i-1}) X_i and its derivative, both times g1 / 2
+  T2 hfp = mk<T2>(0, 0), hdfp = mk<T2>(0, 0);
+  sfor<1, K>([&](auto I) {
+    constexpr int i = I;
+    constexpr double c = raise_c<F>(i);
+    acc_cjmul(hfp, x[i - 1], x[i], (T)c);
+    acc_cjmul2(hdfp, z[i - 1], x[i], x[i - 1], z[i], (T)c);
+  });
+  const T g1h = T(0.5) * (T)p.g[1];
+  hfp = cscale(hfp, g1h);
+  hdfp = cscale(hdfp, g1h);
+  const T cz0 = (T)p.g[0] * rho, cfz = (T)p.g[1] * fz;
+  const T cx0 = T(2) * (T)p.g[0] * drho, cdfz = T(2) * (T)p.g[1] * dfz;
+  // singlet amplitude A00 = sum s_i X_i X_{K-1-i} and dA00 = 2 sum s_i X_i Z_{K-1-i}, times g2
+  T2 sa = mk<T2>(0, 0), sda = mk<T2>(0, 0);
   if constexpr (F >= 2) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) da00 = cadd(da00, cscale(cmul(x[i], z[K - 1 - i]), T(2) * (T)singlet_s<F>(i)));
+    sfor<0, F>([&](auto I) {
+      constexpr int i = I;
+      constexpr double s2 = 2.0 * singlet_s<F>(i);
+      acc_mul(sa, x[i], x[K - 1 - i], (T)s2);
+      acc_mul2(sda, x[i], z[K - 1 - i], x[K - 1 - i], z[i], (T)s2);
+    });
+    constexpr double sm = singlet_s<F>(F);
+    acc_mul(sa, x[F], x[F], (T)sm);
+    acc_mul(sda, x[F], z[F], (T)(2.0 * sm));
+    sa = cscale(sa, (T)p.g[2]);
+    sda = cscale(sda, (T)p.g[2]);
   }
-  T2 da2[5];
+  // quintet amplitudes A2m = sum a_m(i) X_i X_k (k = 8 - mi - i) and dA2m = 2 sum a_m(i) X_i Z_k, times g3
+  T2 b2[5], db2[5];
   if constexpr (F == 3) {
-#pragma unroll
-    for (int mi = 0; mi < 5; ++mi) {
-      T2 s = mk<T2>(0, 0);
-#pragma unroll
-      for (int i = 0; i < 7; ++i) {
-        const int k = 8 - mi - i;
-        if (k >= 0 && k < 7) s = cadd(s, cscale(cmul(x[i], z[k]), T(2) * (T)a2coef(mi, i)));
-      }
-      da2[mi] = s;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    T2 w = cscale(z[i], T(2) * (v + (T)p.zee[i]) + zcoef[i]);
-    T2 nl = cadd(cscale(z[i], (T)p.g[0] * d.rho), cscale(x[i], (T)p.g[0] * drho));
-    nl = cadd(nl, cscale(cadd(ffy<T, F>(d.fz, d.fp, z, i), ffy<T, F>(dfz, dfp, x, i)), (T)p.g[1]));
-    if constexpr (F >= 2) {
-      const T sc = (T)p.g[2] * (T)singlet_s<F>(i);
-      nl = cadd(nl, cscale(cadd(cmulc(z[K - 1 - i], d.a00), cmulc(x[K - 1 - i], da00)), sc));
-    }
-    if constexpr (F == 3) {
-#pragma unroll
-      for (int mi = 0; mi < 5; ++mi) {
-        const int k = 8 - mi - i;
-        if (k >= 0 && k < 7) {
-          const T sc = (T)p.g[3] * (T)a2coef(mi, i);
-          nl = cadd(nl, cscale(cadd(cmulc(z[k], d.a2[mi]), cmulc(x[k], da2[mi])), sc));
+    sfor<0, 5>([&](auto MI) {
+      constexpr int mi = MI;
+      T2 b = mk<T2>(0, 0), db = mk<T2>(0, 0);
+      sfor<0, 7>([&](auto I) {
+        constexpr int i = I;
+        constexpr int k = 8 - mi - i;
+        if constexpr (k >= 0 && k < 7 && i <= k && a2coef(mi, i) != 0.0) {
+          constexpr double a = a2coef(mi, i);
+          if constexpr (i < k) {
+            acc_mul(b, x[i], x[k], (T)(2.0 * a));
+            acc_mul2(db, x[i], z[k], x[k], z[i], (T)(2.0 * a));
+          } else {
+            acc_mul(b, x[i], x[i], (T)a);
+            acc_mul(db, x[i], z[i], (T)(2.0 * a));
+          }
         }
-      }
-    }
-    sink(i, cadd(w, nl));   // q_i is consumed at once, never held for all i
+      });
+      b2[mi] = cscale(b, (T)p.g[3]);
+      db2[mi] = cscale(db, (T)p.g[3]);
+    });
   }
+  sfor<0, K>([&](auto I) {
+    constexpr int i = I;
+    constexpr T l = T(F - i);
+    const T cz = T(2) * (v + (T)p.zee[i]) + zcoef[i] + cz0 + l * cfz;
+    const T cx = cx0 + l * cdfz;
+    T2 q = mk<T2>(cz * z[i].x + cx * x[i].x, cz * z[i].y + cx * x[i].y);
+    // spin-density terms: ((F.f) Z + (dF.f) X)_i, the F_z part folded into cz and cx above
+    if constexpr (i + 1 < K) acc_cjmul2(q, hfp, z[i + 1], hdfp, x[i + 1], (T)raise_c<F>(i + 1));
+    if constexpr (i >= 1) acc_mul2(q, hfp, z[i - 1], hdfp, x[i - 1], (T)raise_c<F>(i));
+    if constexpr (F >= 2) acc_cjmul2(q, z[K - 1 - i], sa, x[K - 1 - i], sda, (T)singlet_s<F>(i));
+    if constexpr (F == 3) {
+      sfor<0, 5>([&](auto MI) {
+        constexpr int mi = MI;
+        constexpr int k = 8 - mi - i;
+        if constexpr (k >= 0 && k < 7 && a2coef(mi, i) != 0.0)
+          acc_cjmul2(q, z[k], b2[mi], x[k], db2[mi], (T)a2coef(mi, i));
+      });
+    }
+    sink(i, q);   // q_i is consumed at once, never held for all i
+  });
 }
 
 }  // namespace gpe
