@@ -93,7 +93,7 @@ typedef struct gpe_solve_opts {
   int ls_max;            /* backtracks per search (30) */
   int cg_maxit;          /* truncated-CG iterations per subproblem (500) */
   double cg_T, cg_theta; /* CG stop ||r|| <= min(T, ||g||^theta) ||g|| (0.1, 1) */
-  int max_reject_streak; /* consecutive ARNT rejections that end the run (12) */
+  int max_reject_streak; /* consecutive ARNT rejections that end the run (30) */
   double sigma_hat_min;  /* lower bound of sigma_hat (1e-8) */
   int verbose;           /* 1: one line per outer iteration on stderr */
   double time_limit;     /* seconds of wall clock after which the run stops unconverged (0: none) */

@@ -32,7 +32,7 @@ gradient norm; and when the predicted decrease |<grad, xi>| is itself below
 16 eps |E| the Armijo search (whose model values are then rounding noise) is
 skipped and the full step alpha0 xi is tried; that trial has no model value,
 so unless its energy change is also below 16 eps |E| (the gradient-norm rule
-above) it is accepted if and only if the energy decreases.  Twelve rejections
+above) it is accepted if and only if the energy decreases.  Thirty rejections
 in a row end
 the run unconverged.  sigma_hat never drops below 1e-8 (repeated very
 successful steps would otherwise drive it to underflow, after which the
@@ -74,7 +74,7 @@ class SolveOpts:
     cg_T: float = 0.1
     cg_theta: float = 1.0
     sigma_hat_min: float = 1e-8
-    max_reject_streak: int = 12
+    max_reject_streak: int = 30
 
 
 @dataclass

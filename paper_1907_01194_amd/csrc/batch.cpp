@@ -61,7 +61,7 @@ gpe_status ops(gpe_batch* b, const std::vector<A>& recs, const std::vector<int>&
 }
 
 gpe_status fin(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const std::vector<double*>& gram,
-               const std::vector<SlotCounts>& nb, bool pstride) {
+               const std::vector<SlotCounts>& nb, bool pstride, bool cg = false) {
   gpe_handle* h0 = b->hs[0];
   std::vector<FinArgs> recs(g.size());
   for (size_t i = 0; i < g.size(); ++i) {
@@ -69,7 +69,7 @@ gpe_status fin(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const
     const size_t stride = pstride ? h->pstride : (size_t)h->nblk;
     for (int q = 0; q < nq; ++q)
       if (nb[i].nb[q] < 0 || (size_t)nb[i].nb[q] > stride) return fail(h0, GPE_EINVAL, "finalize: slot count");
-    recs[i] = FinArgs{h->part, h->res, gram[i], h->ticket, stride, nb[i]};
+    recs[i] = FinArgs{h->part, h->res, gram[i], h->ticket, stride, nb[i], cg ? h->res + CG_DONE : nullptr};
   }
   const void* d = nullptr;
   GPE_TRY(b->sg.put(h0, b->st, recs.data(), sizeof(FinArgs) * recs.size(), &d));
@@ -84,10 +84,11 @@ SlotCounts all_slots(int v) {
 }
 
 // finalize over each problem's nblk reduction workgroups
-gpe_status fin_nblk(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const std::vector<double*>& gram) {
+gpe_status fin_nblk(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const std::vector<double*>& gram,
+                    bool cg = false) {
   std::vector<SlotCounts> nb(g.size());
   for (size_t i = 0; i < g.size(); ++i) nb[i] = all_slots(g[i].c->h->nblk);
-  return fin(b, g, nq, post, gram, nb, false);
+  return fin(b, g, nq, post, gram, nb, false, cg);
 }
 
 std::vector<double*> no_gram(size_t n) { return std::vector<double*>(n, nullptr); }
@@ -106,7 +107,7 @@ gpe_status lap_all(gpe_batch* b, const std::vector<Item>& g, const std::vector<c
       const gpe_handle* h = g[i].c->h;
       const LapAxis& ax = h->ax[a];
       recs[i] = LapArgs<T>{in[i], a == 0 ? nullptr : out[i], out[i], twid<T>(ax), nullptr, nullptr, nullptr,
-                           ax.lamc, ax.nlines, h->npts, 0, ax.inner, ax.n};
+                           ax.lamc, ax.nlines, h->npts, 0, ax.inner, ax.n, nullptr};
       nb[i] = lap_batch_blocks(ax.n, ax.nlines);
     }
     GPE_TRY(launch_records(b, recs, nb, [&](const LapArgs<T>* d, const Span& sp) {
@@ -275,7 +276,15 @@ gpe_status elementwise(gpe_batch* b, std::vector<Item>& g, A (*rec)(const Req&),
 }
 
 template <typename TO> DiffArgs<double, double, TO> diff_rec(const Req& r) { return {r.a, r.b, r.c, r.n}; }
-template <typename T> AxpbyArgs<T> axpby_rec(const Req& r) { return {r.a, r.c, r.s0, r.s1, r.n}; }
+// the CG direction update takes beta from the problem's CG state and stops with it
+template <typename T> AxpbyArgs<T> axpby_rec(const Req& r) {
+  AxpbyArgs<T> a{r.a, r.c, r.s0, r.s1, r.n};
+  if (r.cg) {
+    a.bdev = r.dres + CG_BETA;
+    a.skip = r.dres + CG_DONE;
+  }
+  return a;
+}
 template <typename TI, typename TO> ConvArgs<TI, TO> copy_rec(const Req& r) { return {r.a, r.c, r.n}; }
 
 gpe_status ex_diff(gpe_batch* b, std::vector<Item>& g) {
@@ -317,7 +326,7 @@ gpe_status ex_lap(gpe_batch* b, std::vector<Item>& g) {
 // Batched HVP: fused x pass, projection coefficients, remaining axis passes
 // with the projection in the last one, kappa (same stages as hvp_enq).
 template <typename T>
-gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem) {
+gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
   const size_t m = g.size();
   std::vector<XpassArgs<T>> xr(m);
   std::vector<int> xb(m);
@@ -329,7 +338,8 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem) {
     const bool w64 = sizeof(T) == 8;
     xr[i] = XpassArgs<T>{w64 ? h->Xp : h->Xp32, r.a, w64 ? h->LX64 : h->LX32,
                          w64 ? (const void*)h->V64 : (const void*)h->V32, r.c, twid<T>(h->ax[0]), h->part,
-                         h->ax[0].lamc, h->npts, h->pstride, h->ax[0].n, hvp_params(h, riem, r.s0)};
+                         h->ax[0].lamc, h->npts, h->pstride, h->ax[0].n, hvp_params(h, riem, r.s0),
+                         cg ? h->res + CG_DONE : nullptr};
     xb[i] = xpass_batch_blocks(h->ax[0].n, h->F, b->xvar, h->npts);
     for (int q = 0; q < 7; ++q) nb[i].nb[q] = xb[i];
   }
@@ -338,7 +348,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem) {
   }));
   std::vector<double*> gram(m);
   for (size_t i = 0; i < m; ++i) gram[i] = g[i].c->h->gram_pt;
-  if (riem) GPE_TRY(fin(b, g, 7, POST_HVP_AB, gram, nb, true));
+  if (riem) GPE_TRY(fin(b, g, 7, POST_HVP_AB, gram, nb, true, cg));
   int nq = 7;
   if (b->dim == 1) {
     if (riem) {
@@ -362,7 +372,8 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem) {
         const LapAxis& ax = h->ax[a];
         const Req& r = *g[i].r;
         lr[i] = LapArgs<T>{r.a, r.c, r.c, twid<T>(ax), proj ? (sizeof(T) == 8 ? h->Xp : h->Xp32) : nullptr,
-                           h->res + 32, h->part, ax.lamc, ax.nlines, h->npts, h->pstride, ax.inner, ax.n};
+                           h->res + 32, h->part, ax.lamc, ax.nlines, h->npts, h->pstride, ax.inner, ax.n,
+                           cg ? h->res + CG_DONE : nullptr};
         lb[i] = lap_batch_blocks(ax.n, ax.nlines);
         nb[i].nb[6 + a] = lb[i];
       }
@@ -372,20 +383,22 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem) {
       nq = 7 + a;
     }
   }
-  return fin(b, g, nq, riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E, gram, nb, true);
+  return fin(b, g, nq, cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E, gram, nb, true, cg);
 }
 
 gpe_status ex_hvp(gpe_batch* b, std::vector<Item>& g) {
   if (!b || g.size() == 1) {
-    for (auto& it : g) GPE_TRY(hvp_enq(it.c->h, it.r->a, it.r->c, it.r->flag, it.r->s0));
+    for (auto& it : g) GPE_TRY(hvp_enq(it.c->h, it.r->a, it.r->c, it.r->flag, it.r->s0, it.r->cg));
     return GPE_OK;
   }
-  return b->prec == GPE_MIXED ? hvp_batched<float>(b, g, g[0].r->flag) : hvp_batched<double>(b, g, g[0].r->flag);
+  const bool riem = g[0].r->flag, cg = g[0].r->cg;
+  if (cg && !riem) return fail(g[0].c->h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
+  return b->prec == GPE_MIXED ? hvp_batched<float>(b, g, riem, cg) : hvp_batched<double>(b, g, riem, cg);
 }
 
 gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
   if (!b || g.size() == 1) {
-    for (auto& it : g) GPE_TRY(cg_enq(it.c->h, it.r->s0, it.r->a, it.r->b, it.r->c, it.r->d));
+    for (auto& it : g) GPE_TRY(cg_step_enq(it.c->h, it.r->a, it.r->b, it.r->c, it.r->d));
     return GPE_OK;
   }
   auto run = [&](auto tag) -> gpe_status {
@@ -395,13 +408,24 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
     for (size_t i = 0; i < g.size(); ++i) {
       const gpe_handle* h = g[i].c->h;
       const Req& r = *g[i].r;
-      recs[i] = A{r.a, r.b, r.c, r.d, h->part, r.s0, h->nel};
+      recs[i] = A{r.a, r.b, r.c, r.d, h->part, 0.0, h->nel, h->res + CG_ALPHA, h->res + CG_DONE};
       nb[i] = h->nblk;
     }
     return ops(b, recs, nb);
   };
   GPE_TRY(b->prec == GPE_MIXED ? run(CgArgs<float>{}) : run(CgArgs<double>{}));
-  return fin_nblk(b, g, 1, POST_NONE, no_gram(g.size()));
+  return fin_nblk(b, g, 1, POST_CG_STEP, no_gram(g.size()), true);
+}
+
+gpe_status ex_cginit(gpe_batch* b, std::vector<Item>& g) {
+  if (!b || g.size() == 1) {
+    for (auto& it : g) GPE_TRY(cg_init_enq(it.c->h, it.r->s0, it.r->s1, (int)it.r->n));
+    return GPE_OK;
+  }
+  std::vector<CgInitArgs> recs(g.size());
+  std::vector<int> nb(g.size(), 1);
+  for (size_t i = 0; i < g.size(); ++i) recs[i] = CgInitArgs{g[i].c->h->res, g[i].r->s0, g[i].r->s1, (int)g[i].r->n};
+  return ops(b, recs, nb);
 }
 
 gpe_status execute(gpe_batch* b, int kind, std::vector<Item>& g) {
@@ -417,6 +441,7 @@ gpe_status execute(gpe_batch* b, int kind, std::vector<Item>& g) {
     case RQ_LAP: return ex_lap(b, g);
     case RQ_HVP: return ex_hvp(b, g);
     case RQ_CG: return ex_cg(b, g);
+    case RQ_CGINIT: return ex_cginit(b, g);
     default: return fail(g[0].c->h, GPE_EINVAL, "unknown queued operation");
   }
 }
@@ -424,7 +449,7 @@ gpe_status execute(gpe_batch* b, int kind, std::vector<Item>& g) {
 // Requests with the same key can share one batched launch.
 unsigned key_of(const Req& r) {
   return (unsigned)r.kind | (r.a32 << 8) | (r.b32 << 9) | (r.c32 << 10) | (r.flag << 11) | ((r.a != nullptr) << 12) |
-         ((r.b != nullptr) << 13) | ((r.c != nullptr) << 14);
+         ((r.b != nullptr) << 13) | ((r.c != nullptr) << 14) | (r.cg << 15);
 }
 
 void resume(Ctx* c) {
@@ -551,7 +576,7 @@ static gpe_status tune_batch(gpe_batch* b) {
           const bool w64 = sizeof(T) == 8;
           xr[i] = XpassArgs<T>{w64 ? h->Xp : h->Xp32, w64 ? h->T64 : h->T32, w64 ? h->LX64 : h->LX32,
                                w64 ? (const void*)h->V64 : (const void*)h->V32, h->Gp, twid<T>(h->ax[0]), h->part,
-                               h->ax[0].lamc, h->npts, h->pstride, h->ax[0].n, h->pw};
+                               h->ax[0].lamc, h->npts, h->pstride, h->ax[0].n, h->pw, nullptr};
           xb[i] = xpass_batch_blocks(h->ax[0].n, h->F, v, h->npts);
         }
         return launch_records(b, xr, xb, [&](const XpassArgs<T>* d, const Span& sp) {

@@ -50,7 +50,7 @@ lap_batched_kernel(const LapArgs<T>* __restrict__ args, const int* __restrict__ 
     lap_body<T, NN>(reinterpret_cast<const T2*>(a.in), reinterpret_cast<const T2*>(a.acc),                    \
                     reinterpret_cast<T2*>(a.out), reinterpret_cast<const T2*>(a.tw), a.nlines, a.inner,       \
                     (T)a.lamc, F, a.npts, reinterpret_cast<const T2*>(a.X), a.coef, a.part, a.stride, slot,   \
-                    blk);                                                                                     \
+                    blk, a.skip);                                                                             \
     break;
     GPE_BSIZES(GPE_CASE)
 #undef GPE_CASE
@@ -111,7 +111,7 @@ xpass_batched_kernel(const XpassArgs<T>* __restrict__ args, const int* __restric
     xpass_body<T, NN, F, VAR>(reinterpret_cast<const T2*>(a.X), reinterpret_cast<const T2*>(a.Z),                \
                               reinterpret_cast<const T2*>(a.Y), reinterpret_cast<const T*>(a.V),                  \
                               reinterpret_cast<T2*>(a.W), reinterpret_cast<const T2*>(a.tw), (long)(a.npts / NN), \
-                              a.npts, (T)a.lamc, a.p, a.part, a.stride, blk);                                     \
+                              a.npts, (T)a.lamc, a.p, a.part, a.stride, blk, a.skip);                             \
     break;
     GPE_BSIZES(GPE_CASE)
 #undef GPE_CASE

@@ -14,9 +14,11 @@ namespace gpe {
 constexpr int kFinThreads = 256;
 
 __device__ void finalize_body(const double* __restrict__ part, size_t stride, const SlotCounts& nb, int nq,
-                              double* __restrict__ res, int post, int F, double* gram, unsigned int* ticket, int q) {
+                              double* __restrict__ res, int post, int F, double* gram, unsigned int* ticket, int q,
+                              const double* skip) {
   __shared__ double red[kFinThreads / kWave];
   __shared__ bool last;
+  if (skip && *skip != 0.0) return;   // uniform over the launch: no ticket is taken
   const double* pq = part + (size_t)q * stride;
   const int n = nb.nb[q];
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -71,26 +73,51 @@ __device__ void finalize_body(const double* __restrict__ part, size_t stride, co
     const double det = a11 * a22 - a12 * a12;
     res[32] = (a22 * out[0] - a12 * out[1]) / det;
     res[33] = (a11 * out[1] - a12 * out[0]) / det;
-  } else if (post == POST_HVP_KAPPA || post == POST_HVP_KAPPA_E) {
+  } else if (post == POST_HVP_KAPPA || post == POST_HVP_KAPPA_E || post == POST_CG_KAPPA) {
     double zlz = 0.0;
     for (int k = 6; k < nq; ++k) zlz += out[k];
-    double kappa = out[4] + zlz;
-    if (post == POST_HVP_KAPPA) kappa -= out[32] * out[2] + out[33] * out[3];
+    const double kappa = post == POST_HVP_KAPPA_E ? out[4] + zlz
+                                                  : out[4] + zlz - out[32] * out[2] - out[33] * out[3];
+    const double pp = out[5];
     res[34] = kappa;
-    res[35] = out[5];
+    res[35] = pp;
+    if (post == POST_CG_KAPPA) {
+      res[CG_IT] = out[CG_IT] + 1.0;
+      if (!(kappa > out[CG_EPS] * pp)) {   // curvature stop (a NaN stops too)
+        res[CG_KAPPA] = kappa;
+        res[CG_PP] = pp;
+        res[CG_REASON] = CG_STOP_CURVATURE;
+        res[CG_DONE] = 1.0;
+      } else {
+        res[CG_ALPHA] = out[CG_RR] / kappa;
+      }
+    }
+  } else if (post == POST_CG_STEP) {
+    const double rr = out[0];
+    if (sqrt(rr) <= out[CG_TOL]) {
+      res[CG_REASON] = CG_STOP_RESIDUAL;
+      res[CG_DONE] = 1.0;
+    } else {
+      res[CG_BETA] = rr / out[CG_RR];
+      res[CG_RR] = rr;
+      if (out[CG_IT] >= out[CG_MAXIT]) {
+        res[CG_REASON] = CG_STOP_CAP;
+        res[CG_DONE] = 1.0;
+      }
+    }
   }
 }
 
 __global__ void __launch_bounds__(kFinThreads)
 finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, int nq, double* __restrict__ res,
-                int post, int F, double* gram, unsigned int* ticket) {
-  finalize_body(part, stride, nb, nq, res, post, F, gram, ticket, blockIdx.x);
+                int post, int F, double* gram, unsigned int* ticket, const double* skip) {
+  finalize_body(part, stride, nb, nq, res, post, F, gram, ticket, blockIdx.x, skip);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
 finalize_batched_kernel(const FinArgs* __restrict__ args, int nq, int post, int F) {
   const FinArgs& a = args[blockIdx.y];
-  finalize_body(a.part, a.stride, a.nb, nq, a.res, post, F, a.gram, a.ticket, blockIdx.x);
+  finalize_body(a.part, a.stride, a.nb, nq, a.res, post, F, a.gram, a.ticket, blockIdx.x, a.skip);
 }
 
 static bool counts_ok(const SlotCounts& nb, int nq, size_t stride) {
@@ -101,10 +128,10 @@ static bool counts_ok(const SlotCounts& nb, int nq, size_t stride) {
 }
 
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post, int F,
-                    double* gram, unsigned int* ticket, hipStream_t st) {
+                    double* gram, unsigned int* ticket, const double* skip, hipStream_t st) {
   if (!counts_ok(nb, nq, stride)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(finalize_kernel, dim3(nq), dim3(kFinThreads), 0, st, part, stride, nb, nq, res, post, F, gram,
-                     ticket);
+                     ticket, skip);
   return hipGetLastError();
 }
 
@@ -223,10 +250,12 @@ hipError_t scale_comps(int K, const void* u, const void* xi, double t, const dou
 // ----------------------------------------------------------------- vector updates
 template <typename T>
 __device__ void run_op(const AxpbyArgs<T>& a, int blk, int nblk) {
+  if (a.skip && *a.skip != 0.0) return;
   auto x = reinterpret_cast<const c_t<T>*>(a.x);
   auto y = reinterpret_cast<c_t<T>*>(a.y);
-  const T ca = (T)a.a, cb = (T)a.b;
-  const bool keep = a.b != 0.0;
+  const double bv = a.bdev ? *a.bdev : a.b;
+  const T ca = (T)a.a, cb = (T)bv;
+  const bool keep = bv != 0.0;
   for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     const c_t<T> xv = x[e];
     c_t<T> yv;
@@ -248,11 +277,12 @@ hipError_t axpby(double a, const void* x, double b, void* y, size_t n, hipStream
 
 template <typename T>
 __device__ void run_op(const CgArgs<T>& a, int blk, int nblk) {
+  if (a.skip && *a.skip != 0.0) return;
   auto p = reinterpret_cast<const c_t<T>*>(a.p);
   auto q = reinterpret_cast<const c_t<T>*>(a.q);
   auto z = reinterpret_cast<c_t<T>*>(a.z);
   auto r = reinterpret_cast<c_t<T>*>(a.r);
-  const T ca = (T)a.a;
+  const T ca = (T)(a.adev ? *a.adev : a.a);
   double acc[1] = {0.0};
   for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     const c_t<T> pv = p[e], qv = q[e];
@@ -272,6 +302,18 @@ template <typename T>
 hipError_t cg_update(double a, const void* p, const void* q, void* z, void* r, double* part, int nblk, size_t n,
                      hipStream_t st) {
   return launch_single(CgArgs<T>{p, q, z, r, part, a, n}, nblk, st);
+}
+
+__device__ void run_op(const CgInitArgs& a, int blk, int nblk) {
+  if (blk != 0 || threadIdx.x != 0) return;
+  double* c = a.res;
+  c[CG_RR] = c[0];
+  c[CG_IT] = 0.0;
+  c[CG_TOL] = a.tol;
+  c[CG_EPS] = a.eps;
+  c[CG_MAXIT] = (double)a.maxit;
+  c[CG_REASON] = a.maxit > 0 ? CG_STOP_NONE : CG_STOP_CAP;
+  c[CG_DONE] = a.maxit > 0 ? 0.0 : 1.0;
 }
 
 template <typename TA, typename TB>
@@ -368,6 +410,7 @@ GPE_OP(ConvArgs<double, float>)
 GPE_OP(ConvArgs<float, double>)
 GPE_OP(ConvArgs<double, double>)
 GPE_OP(ConvArgs<float, float>)
+GPE_OP(CgInitArgs)
 
 template hipError_t project<double, double>(int, const void*, const void*, void*, const double*, double*, int, size_t, hipStream_t);
 template hipError_t project<float, float>(int, const void*, const void*, void*, const double*, double*, int, size_t, hipStream_t);

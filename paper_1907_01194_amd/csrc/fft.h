@@ -238,7 +238,9 @@ template <typename T, int N>
 __device__ __forceinline__ void lap_body(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
                                          const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F,
                                          size_t npts, const c_t<T>* __restrict__ X, const double* __restrict__ coef,
-                                         double* __restrict__ part, size_t stride, int slot, long blk) {
+                                         double* __restrict__ part, size_t stride, int slot, long blk,
+                                         const double* skip) {
+  if (skip && *skip != 0.0) return;   // uniform over the workgroup
   using T2 = c_t<T>;
   constexpr int TPL = Geo<N>::TPL;
   constexpr int LPB = Geo<N>::LPB;
@@ -305,7 +307,8 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
                                            const c_t<T>* __restrict__ Y, const T* __restrict__ V,
                                            c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
                                            size_t npts, T lamc, const PwParams& p, double* __restrict__ part,
-                                           size_t stride, long blk) {
+                                           size_t stride, long blk, const double* skip) {
+  if (skip && *skip != 0.0) return;   // uniform over the workgroup
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
   constexpr int TPL = Geo<N>::TPL;

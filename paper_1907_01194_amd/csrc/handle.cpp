@@ -61,7 +61,7 @@ template gpe_status laplacian<float>(gpe_handle*, const void*, void*);
 gpe_status finalize_enq(gpe_handle* h, int nq, int post, double* gram) {
   SlotCounts nb;
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = h->nblk;
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, h->ticket, h->st));
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, h->ticket, nullptr, h->st));
   return GPE_OK;
 }
 
@@ -148,34 +148,41 @@ gpe_status adopt_point(gpe_handle* h) {
   return GPE_OK;
 }
 
+// cg: one iteration of the device-resident truncated CG (the launches are
+// skipped once the CG has stopped, and the last finalize runs its tests).
 template <typename T>
-static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const PwParams& p) {
+static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const PwParams& p, bool cg) {
   const void* Xw = sizeof(T) == 8 ? h->Xp : h->Xp32;
   const void* Yw = sizeof(T) == 8 ? h->LX64 : h->LX32;
   const T* Vw = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h->V64 : (const void*)h->V32);
+  const double* skip = cg ? h->res + CG_DONE : nullptr;
   SlotCounts nb;
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = 0;
   int nbx = 0;
   GPE_KT(h, KK_HVP_XPASS,
-         hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->xvar, h->st));
+         hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->xvar, skip, h->st));
   for (int q = 0; q < 7; ++q) nb.nb[q] = nbx;
   double* coef = h->res + 32;
   if (riem)
-    GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, h->st));
+    GPE_KT(h, KK_FINALIZE,
+           finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, skip, h->st));
   int nq = 7;
   if (h->dim == 1) {
-    if (riem) GPE_KT(h, KK_PROJECT, (project<T, T>(h->F, Xw, HZ, HZ, coef, nullptr, h->nblk, h->npts, h->st)));
+    // (after a CG stop this projection still runs, on an HZ that nothing reads any more)
+    if (riem)
+      GPE_KT(h, KK_PROJECT,
+             launch_single(ProjArgs<T, T, false>{Xw, HZ, HZ, coef, 0.0, 0.0, nullptr, h->npts, h->F}, h->nblk, h->st));
   } else {
     for (int a = 1; a < h->dim; ++a) {
       const bool proj = riem && a == h->dim - 1;
       GPE_KT(h, KK_LAP_X + a,
              lap_axis_ex<T>(h->ax[a], Z, HZ, HZ, h->F, h->npts, proj ? Xw : nullptr, coef, h->part, h->pstride,
-                            6 + a, &nb.nb[6 + a], h->st));
+                            6 + a, &nb.nb[6 + a], skip, h->st));
       nq = 7 + a;
     }
   }
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E, h->F,
-                                  h->gram_pt, h->ticket, h->st));
+  const int post = cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E;
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, post, h->F, h->gram_pt, h->ticket, skip, h->st));
   return GPE_OK;
 }
 
@@ -199,11 +206,13 @@ static gpe_status tune_xpass_t(gpe_handle* h) {
   int bestv = 1;
   for (int v = 0; v < nv; ++v) {
     int nb = 0;
-    GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v, h->st));
+    GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v, nullptr,
+                            h->st));
     float tmin = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       GPE_HIP(h, hipEventRecord(e0, h->st));
-      GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v, h->st));
+      GPE_HIP(h, hvp_xpass<T>(h->F, h->ax[0], h->npts, A, Bz, C, Vw, Wt, h->pw, h->part, h->pstride, &nb, v,
+                              nullptr, h->st));
       GPE_HIP(h, hipEventRecord(e1, h->st));
       GPE_HIP(h, hipEventSynchronize(e1));
       float ms = 0.f;
@@ -232,11 +241,12 @@ PwParams hvp_params(const gpe_handle* h, bool riem, double sigma) {
   return p;
 }
 
-gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma) {
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, bool cg) {
   if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
+  if (cg && !riem) return fail(h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
   const PwParams p = hvp_params(h, riem, sigma);
-  if (h->prec == GPE_FP64) return hvp_t<double>(h, Z, HZ, riem, p);
-  return hvp_t<float>(h, Z, HZ, riem, p);
+  if (h->prec == GPE_FP64) return hvp_t<double>(h, Z, HZ, riem, p, cg);
+  return hvp_t<float>(h, Z, HZ, riem, p, cg);
 }
 
 gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz) {
@@ -247,7 +257,7 @@ gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz) {
 }
 
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
-  GPE_TRY(hvp_enq(h, Z, HZ, riem, sigma));
+  GPE_TRY(hvp_enq(h, Z, HZ, riem, sigma, false));
   if (!kappa && !zz) return GPE_OK;
   GPE_TRY(fetch(h));
   return hvp_read(h, kappa, zz);
@@ -425,10 +435,51 @@ gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool 
   return dot_read(h, out);
 }
 
-gpe_status cg_enq(gpe_handle* h, double alpha, const void* p, const void* q, void* z, void* r) {
-  if (h->prec == GPE_MIXED) GPE_KT(h, KK_VECTOR, cg_update<float>(alpha, p, q, z, r, h->part, h->nblk, h->nel, h->st));
-  else GPE_KT(h, KK_VECTOR, cg_update<double>(alpha, p, q, z, r, h->part, h->nblk, h->nel, h->st));
-  return finalize_enq(h, 1, POST_NONE, nullptr);
+gpe_status cg_init_enq(gpe_handle* h, double tol, double eps, int maxit) {
+  GPE_KT(h, KK_VECTOR, launch_single(CgInitArgs{h->res, tol, eps, maxit}, 1, h->st));
+  return GPE_OK;
+}
+
+template <typename T>
+static gpe_status cg_step_t(gpe_handle* h, const void* p, const void* q, void* z, void* r) {
+  CgArgs<T> a{p, q, z, r, h->part, 0.0, h->nel};
+  a.adev = h->res + CG_ALPHA;
+  a.skip = h->res + CG_DONE;
+  GPE_KT(h, KK_VECTOR, launch_single(a, h->nblk, h->st));
+  SlotCounts nb;
+  for (int k = 0; k < kMaxQ; ++k) nb.nb[k] = h->nblk;
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, 1, h->res, POST_CG_STEP, h->F, nullptr, h->ticket,
+                                  h->res + CG_DONE, h->st));
+  return GPE_OK;
+}
+
+template <typename T>
+static gpe_status cg_dir_t(gpe_handle* h, const void* r, void* p) {
+  AxpbyArgs<T> a{r, p, -1.0, 0.0, h->nel};
+  a.bdev = h->res + CG_BETA;
+  a.skip = h->res + CG_DONE;
+  GPE_KT(h, KK_VECTOR, launch_single(a, elementwise_blocks(h->nel), h->st));
+  return GPE_OK;
+}
+
+gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r) {
+  return h->prec == GPE_MIXED ? cg_step_t<float>(h, p, q, z, r) : cg_step_t<double>(h, p, q, z, r);
+}
+
+gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p) {
+  return h->prec == GPE_MIXED ? cg_dir_t<float>(h, r, p) : cg_dir_t<double>(h, r, p);
+}
+
+gpe_status cg_state_read(gpe_handle* h, CgState* cs) {
+  const double* c = h->hres;
+  cs->done = c[CG_DONE] != 0.0;
+  cs->reason = (int)c[CG_REASON];
+  cs->iters = (int)c[CG_IT];
+  cs->kappa = c[CG_KAPPA];
+  cs->pp = c[CG_PP];
+  if (cs->done && cs->reason == CG_STOP_CURVATURE) GPE_TRY(finite(h, c + CG_KAPPA, 2, "the CG curvature"));
+  GPE_TRY(finite(h, c + CG_RR, 1, "the CG residual"));
+  return GPE_OK;
 }
 
 // Interpolation matrix of the Fourier interpolant from n nodes to the 2n nodes
@@ -524,7 +575,7 @@ void gpe_solve_opts_default(gpe_solve_opts* o) {
   o->cg_maxit = 500;
   o->cg_T = 0.1;
   o->cg_theta = 1.0;
-  o->max_reject_streak = 12;
+  o->max_reject_streak = 30;
   o->sigma_hat_min = 1e-8;
   o->verbose = 0;
   o->time_limit = 0.0;

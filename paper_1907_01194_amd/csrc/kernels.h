@@ -53,10 +53,12 @@ hipError_t pw_grad(int F, const void* X, const void* LX, const T* V, void* G, do
 //   [6] <Z, L_x Z> (Parseval).
 // Returns the number of workgroups (partials per slot) in *nblk_out.
 // var: schedule variant (rows per workgroup), 0 .. xpass_variants(n)-1; 1 is the default.
+// skip (all the launches below that take one): a device flag; when it is
+// nonzero at launch time every workgroup returns at once (null: never).
 template <typename T>
 hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
                      const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nblk_out, int var,
-                     hipStream_t st);
+                     const double* skip, hipStream_t st);
 int xpass_variants(int n);
 
 // Axis pass with Parseval partial <Z, L_a Z> into part[slot * stride + wg] and,
@@ -64,7 +66,7 @@ int xpass_variants(int n);
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nblk_out,
-                       hipStream_t st);
+                       const double* skip, hipStream_t st);
 size_t lap_max_blocks(const LapAxis& ax, int K);
 
 // Post-processing done by the single-block finalize kernel after summing the
@@ -82,13 +84,38 @@ enum PostOp {
   // writes kappa = <Z, HZ> to res[34] and ||Z||^2 to res[35].
   POST_HVP_KAPPA = 3,
   // as POST_HVP_KAPPA for a Euclidean HVP: no projection, res[32..33] unused
-  POST_HVP_KAPPA_E = 4
+  POST_HVP_KAPPA_E = 4,
+  // truncated CG on the device (state in res[CG_*]): POST_HVP_KAPPA, then one
+  // more HVP is counted and either the curvature test stops the CG or
+  // alpha = rr / kappa
+  POST_CG_KAPPA = 5,
+  // after the CG update (res[0] = ||r||^2): the residual test stops the CG,
+  // else beta = ||r||^2 / rr, rr = ||r||^2, and the iteration cap stops it
+  POST_CG_STEP = 6
 };
+
+// Device-resident state of the truncated CG of the Newton model, in a
+// handle's res array (doubles): the stop flag doubles as the skip flag of every
+// launch of the CG iteration, so the host can queue several iterations at once.
+enum CgSlot {
+  CG_RR = 40,     // current ||r||^2
+  CG_ALPHA,       // step of the last CG update
+  CG_BETA,        // direction coefficient of the last update
+  CG_DONE,        // 0 while running, 1 once stopped
+  CG_IT,          // HVPs done (one per iteration)
+  CG_KAPPA,       // kappa and ||p||^2 at a curvature stop
+  CG_PP,
+  CG_REASON,      // CG_STOP_*
+  CG_TOL,         // residual tolerance
+  CG_EPS,         // curvature threshold factor: stop when kappa <= eps ||p||^2
+  CG_MAXIT        // iteration cap
+};
+enum CgStop { CG_STOP_NONE = 0, CG_STOP_CURVATURE = 1, CG_STOP_RESIDUAL = 2, CG_STOP_CAP = 3 };
 // Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
 // (deterministic), then apply `post`.  ticket: a device counter that is 0
 // between launches (the launch leaves it at 0).
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post,
-                    int F, double* gram, unsigned int* ticket, hipStream_t st);
+                    int F, double* gram, unsigned int* ticket, const double* skip, hipStream_t st);
 
 // out_i = W_i - (coef[0] + coef[1] l_i) X_i (coef on the device).  X is c128
 // or c64 as TX; W/out in T.  If part != null, partial sums of ||out||^2 (nq = 1).
@@ -149,6 +176,8 @@ template <typename T> struct AxpbyArgs {   // y = a x + b y; b == 0: y = a x (y 
   void* y;
   double a, b;
   size_t n;
+  const double* bdev = nullptr;   // b from device memory when set
+  const double* skip = nullptr;
 };
 template <typename T> struct CgArgs {      // z += a p; r += a q; partials of ||r||^2
   const void* p;
@@ -158,6 +187,15 @@ template <typename T> struct CgArgs {      // z += a p; r += a q; partials of ||
   double* part;
   double a;
   size_t n;
+  const double* adev = nullptr;   // a from device memory when set
+  const double* skip = nullptr;
+};
+// Start of a device-resident CG: rr = res[0] (the preceding reduction), not
+// stopped, no iteration yet, with the given tolerance, curvature factor and cap.
+struct CgInitArgs {
+  double* res;
+  double tol, eps;
+  int maxit;
 };
 template <typename TA, typename TB> struct DotArgs {   // partials of <a, b>
   const void* a;
@@ -228,6 +266,7 @@ struct FinArgs {
   unsigned int* ticket;
   size_t stride;
   SlotCounts nb;
+  const double* skip;
 };
 hipError_t finalize_batched(const FinArgs* args, int nprob, int nq, int post, int F, hipStream_t st);
 
@@ -247,6 +286,7 @@ template <typename T> struct LapArgs {
   size_t stride;
   int inner;
   int n;
+  const double* skip;
 };
 template <typename T>
 hipError_t lap_batched(const LapArgs<T>* args, const Span& sp, int F, int slot, hipStream_t st);
@@ -267,6 +307,7 @@ template <typename T> struct XpassArgs {
   size_t stride;
   int n;
   PwParams p;
+  const double* skip;
 };
 template <typename T>
 hipError_t xpass_batched(int F, int var, const XpassArgs<T>* args, const Span& sp, hipStream_t st);

@@ -20,22 +20,22 @@ __global__ void __launch_bounds__(Geo<N>::THREADS)
 lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
                 const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F, size_t npts,
                 const c_t<T>* __restrict__ X, const double* __restrict__ coef, double* __restrict__ part,
-                size_t stride, int slot) {
-  lap_body<T, N>(in, acc, out, twg, nlines, inner, lamc, F, npts, X, coef, part, stride, slot, blockIdx.x);
+                size_t stride, int slot, const double* skip) {
+  lap_body<T, N>(in, acc, out, twg, nlines, inner, lamc, F, npts, X, coef, part, stride, slot, blockIdx.x, skip);
 }
 
 template <typename T, int N, int F, int VAR>
 __global__ void __launch_bounds__((XGeo<N, 2 * F + 1, VAR>::THREADS))
 hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, const c_t<T>* __restrict__ Y,
                  const T* __restrict__ V, c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
-                 size_t npts, T lamc, PwParams p, double* __restrict__ part, size_t stride) {
-  xpass_body<T, N, F, VAR>(X, Z, Y, V, W, twg, nrows, npts, lamc, p, part, stride, blockIdx.x);
+                 size_t npts, T lamc, PwParams p, double* __restrict__ part, size_t stride, const double* skip) {
+  xpass_body<T, N, F, VAR>(X, Z, Y, V, W, twg, nrows, npts, lamc, p, part, stride, blockIdx.x, skip);
 }
 
 template <typename T, int N>
 static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       hipStream_t st) {
+                       const double* skip, hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int LPB = Geo<N>::LPB;
   const long nlines = ax.nlines;
@@ -45,7 +45,7 @@ static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void*
   hipLaunchKernelGGL((lap_axis_kernel<T, N>), dim3(grid), dim3(Geo<N>::THREADS), lds, st,
                      reinterpret_cast<const T2*>(in), reinterpret_cast<const T2*>(acc),
                      reinterpret_cast<T2*>(out), tw, nlines, ax.inner, (T)ax.lamc, F, npts,
-                     reinterpret_cast<const T2*>(X), coef, part, stride, slot);
+                     reinterpret_cast<const T2*>(X), coef, part, stride, slot, skip);
   if (nb) *nb = grid;
 }
 
@@ -55,7 +55,7 @@ template <typename T>
 hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st) {
   switch (ax.n) {
 #define GPE_CASE(NN) \
-  case NN: launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, st); break;
+  case NN: launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, st); break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -66,10 +66,10 @@ hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* ou
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       hipStream_t st) {
+                       const double* skip, hipStream_t st) {
   switch (ax.n) {
 #define GPE_CASE(NN) \
-  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, st); break;
+  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, skip, st); break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -79,7 +79,8 @@ hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void*
 
 template <typename T, int N, int F, int VAR>
 static void launch_xpass(const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y, const T* V,
-                         void* W, const PwParams& p, double* part, size_t stride, int* nb, hipStream_t st) {
+                         void* W, const PwParams& p, double* part, size_t stride, int* nb, const double* skip,
+                         hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
   using G = XGeo<N, K, VAR>;
@@ -93,7 +94,7 @@ static void launch_xpass(const LapAxis& ax, size_t npts, const void* X, const vo
   hipLaunchKernelGGL((hvp_xpass_kernel<T, N, F, VAR>), dim3(grid), dim3(G::THREADS), lds, st,
                      reinterpret_cast<const T2*>(X), reinterpret_cast<const T2*>(Z),
                      reinterpret_cast<const T2*>(Y), V, reinterpret_cast<T2*>(W), tw, nrows, npts, (T)ax.lamc, p,
-                     part, stride);
+                     part, stride, skip);
   *nb = grid;
 }
 
@@ -103,12 +104,12 @@ static constexpr bool tuned_size(int n) { return n == 64 || n == 96 || n == 128 
 template <typename T, int N, int F>
 static void launch_xpass_var(int var, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
                              const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb,
-                             hipStream_t st) {
+                             const double* skip, hipStream_t st) {
   if constexpr (tuned_size(N)) {
-    if (var == 0) return launch_xpass<T, N, F, 0>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
-    if (var == 2) return launch_xpass<T, N, F, 2>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
+    if (var == 0) return launch_xpass<T, N, F, 0>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st);
+    if (var == 2) return launch_xpass<T, N, F, 2>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st);
   }
-  launch_xpass<T, N, F, 1>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, st);
+  launch_xpass<T, N, F, 1>(ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st);
 }
 
 int xpass_variants(int n) { return tuned_size(n) ? 3 : 1; }
@@ -116,12 +117,15 @@ int xpass_variants(int n) { return tuned_size(n) ? 3 : 1; }
 template <typename T>
 hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const void* Z, const void* Y,
                      const T* V, void* W, const PwParams& p, double* part, size_t stride, int* nb, int var,
-                     hipStream_t st) {
+                     const double* skip, hipStream_t st) {
   switch (ax.n * 4 + F) {
-#define GPE_CASE(NN)                                                                                            \
-  case NN * 4 + 1: launch_xpass_var<T, NN, 1>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
-  case NN * 4 + 2: launch_xpass_var<T, NN, 2>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break; \
-  case NN * 4 + 3: launch_xpass_var<T, NN, 3>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, st); break;
+#define GPE_CASE(NN)                                                                                          \
+  case NN * 4 + 1: launch_xpass_var<T, NN, 1>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st); \
+    break;                                                                                                    \
+  case NN * 4 + 2: launch_xpass_var<T, NN, 2>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st); \
+    break;                                                                                                    \
+  case NN * 4 + 3: launch_xpass_var<T, NN, 3>(var, ax, npts, X, Z, Y, V, W, p, part, stride, nb, skip, st); \
+    break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -156,13 +160,14 @@ bool lap_size_supported(int n) {
 template hipError_t lap_axis<double>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis<float>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis_ex<double>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
-                                        const double*, double*, size_t, int, int*, hipStream_t);
+                                        const double*, double*, size_t, int, int*, const double*, hipStream_t);
 template hipError_t lap_axis_ex<float>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
-                                       const double*, double*, size_t, int, int*, hipStream_t);
+                                       const double*, double*, size_t, int, int*, const double*, hipStream_t);
 template hipError_t hvp_xpass<double>(int, const LapAxis&, size_t, const void*, const void*, const void*,
                                       const double*, void*, const PwParams&, double*, size_t, int*, int,
-                                      hipStream_t);
+                                      const double*, hipStream_t);
 template hipError_t hvp_xpass<float>(int, const LapAxis&, size_t, const void*, const void*, const void*,
-                                     const float*, void*, const PwParams&, double*, size_t, int*, int, hipStream_t);
+                                     const float*, void*, const PwParams&, double*, size_t, int*, int,
+                                     const double*, hipStream_t);
 
 }  // namespace gpe

@@ -146,7 +146,7 @@ gpe_status adopt_point(gpe_handle* h);
 // HVP at the set point in the work precision; if kappa != null also
 // returns <Z, HZ> and ||Z||^2 (synchronises).
 PwParams hvp_params(const gpe_handle* h, bool riemannian, double sigma);
-gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma);
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, bool cg);
 gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz);
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, double* kappa,
                double* zz);
@@ -171,9 +171,21 @@ gpe_status dot_enq(gpe_handle* h, const void* a, bool a32, const void* b, bool b
 gpe_status dot_read(gpe_handle* h, double* out);
 gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool b32, size_t n, double* out);
 
-// CG step in the work precision: z += alpha p, r += alpha q, ||r||^2 into
-// res[0] (read with dot_read).
-gpe_status cg_enq(gpe_handle* h, double alpha, const void* p, const void* q, void* z, void* r);
+// Device-resident truncated CG (state in h->res[CG_*], see kernels.h), work
+// precision: cg_init_enq after a reduction of ||r||^2 into res[0]; per
+// iteration hvp_enq(..., cg = true), cg_step_enq (z += alpha p, r += alpha q,
+// residual and cap tests) and cg_dir_enq (p = -r + beta p).  After a fetch
+// cg_state_read reports where the CG stands.
+struct CgState {
+  bool done;
+  int reason;    // CG_STOP_*
+  int iters;     // HVPs done
+  double kappa, pp;   // at a curvature stop
+};
+gpe_status cg_init_enq(gpe_handle* h, double tol, double eps, int maxit);
+gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r);
+gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p);
+gpe_status cg_state_read(gpe_handle* h, CgState* cs);
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
 gpe_status tune_xpass(gpe_handle* h);

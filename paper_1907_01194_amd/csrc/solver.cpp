@@ -21,7 +21,8 @@
 //     the trial is accepted (ratio 1) iff it lowers the Riemannian gradient
 //     norm; when |<grad, xi>| <= 16 eps |E| the Armijo search is skipped and
 //     the full step is tried, and if its energy change is resolved it is
-//     accepted iff the energy decreases; 12 rejections in a row end the run;
+//     accepted iff the energy decreases; 30 rejections in a row end the run
+//     (each multiplies sigma by 10: by then a trial is a short gradient step);
 //   * sigma_hat is kept >= sigma_hat_min (1e-8): a run of very successful
 //     steps would otherwise drive it to underflow, and the x10 increases on
 //     rejection could then never restore any regularisation.
@@ -30,6 +31,7 @@
 // retractions and the ratio are FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -182,15 +184,40 @@ Req rq_hvp(const void* Z, void* HZ, bool riem, double sigma, bool w32) {
   r.a32 = r.c32 = w32;
   return r;
 }
-Req rq_cg(double alpha, const void* p, const void* q, void* z, void* res, bool w32) {
+// One iteration of the device-resident truncated CG: A p, the update of z and
+// r with the tests, the new direction p = -r + beta p.
+void push_cg_iteration(Ctx& c, void* p, void* Ap, void* z, void* r, double sigma, bool w32) {
+  Req h;
+  h.kind = RQ_HVP;
+  h.a = p;
+  h.c = Ap;
+  h.flag = true;
+  h.cg = true;
+  h.s0 = sigma;
+  h.a32 = h.c32 = w32;
+  c.push(h);
+  Req u;
+  u.kind = RQ_CG;
+  u.a = p;
+  u.b = Ap;
+  u.c = z;
+  u.d = r;
+  u.a32 = u.c32 = w32;
+  u.cg = true;
+  c.push(u);
+  Req d = rq_axpby(-1.0, r, 0.0, p, w32, c.h->nel);
+  d.cg = true;
+  d.dres = c.h->res;
+  c.push(d);
+}
+
+Req rq_cginit(double tol, double eps, int maxit) {
   Req r;
-  r.kind = RQ_CG;
-  r.s0 = alpha;
-  r.a = p;
-  r.b = q;
-  r.c = z;
-  r.d = res;
-  r.a32 = r.c32 = w32;
+  r.kind = RQ_CGINIT;
+  r.s0 = tol;
+  r.s1 = eps;
+  r.n = (size_t)(maxit > 0 ? maxit : 0);
+  r.cg = true;
   return r;
 }
 
@@ -321,7 +348,9 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     if (o->time_limit > 0 && clk.sec() > o->time_limit) break;
     const double sigma = shat * gn;
 
-    // ---- truncated CG on Hess m_k [xi] = -grad m_k
+    // ---- truncated CG on Hess m_k [xi] = -grad m_k.  Its scalars (alpha, beta,
+    // the curvature, residual and cap tests) live on the device, so a round
+    // queues several iterations; launches after the stop return at once.
     void* r = B[B_R];
     void* p = B[B_P];
     void* Ap = B[B_AP];
@@ -332,41 +361,29 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     c.push(rq_copy(nullptr, w32, cz, w32, n));
     c.push(rq_axpby(-1.0, r, 0.0, p, w32, n));
     c.push(rq_dot(r, w32, r, w32, n));
-    ROUND;
-    double rr;
-    CO_TRY(dot_read(h, &rr));
     const double cg_tol = std::fmin(o->cg_T, std::pow(gn, o->cg_theta)) * gn;
     const double eps_c = 1e-12 * std::fmax(1.0, gn);
+    c.push(rq_cginit(cg_tol, eps_c, o->cg_maxit));
+    CgState cs{};
+    for (int kstep = 2;; kstep = std::min(2 * kstep, 16)) {
+      for (int j = 0; j < kstep; ++j) push_cg_iteration(c, p, Ap, cz, r, sigma, w32);
+      ROUND;
+      CO_TRY(cg_state_read(h, &cs));
+      if (cs.done) break;
+    }
+    st->hvp_calls += cs.iters;
+    st->cg_total += cs.iters;
     bool have_d = false, s_is_mg = false;
     double kappa_d = 0, sigma_est = -1.0;
-    int it = 0;
-    for (; it < o->cg_maxit; ++it) {
-      double kappa, pp;
-      c.push(rq_hvp(p, Ap, true, sigma, w32));
-      ROUND;
-      CO_TRY(hvp_read(h, &kappa, &pp));
-      st->hvp_calls++;
-      st->cg_total++;
-      if (kappa <= eps_c * pp) {
-        if (it == 0) s_is_mg = true;
-        if (kappa < 0) {
-          have_d = true;
-          kappa_d = kappa;
-          sigma_est = std::fabs(kappa) / pp;
-        }
-        break;
+    int it = cs.iters;
+    if (cs.reason == CG_STOP_CURVATURE) {
+      it = cs.iters - 1;                    // the iteration whose curvature stopped the CG
+      if (it == 0) s_is_mg = true;
+      if (cs.kappa < 0) {
+        have_d = true;
+        kappa_d = cs.kappa;
+        sigma_est = std::fabs(cs.kappa) / cs.pp;
       }
-      const double alpha = rr / kappa;
-      c.push(rq_cg(alpha, p, Ap, cz, r, w32));
-      ROUND;
-      double rr_new;
-      CO_TRY(dot_read(h, &rr_new));
-      if (std::sqrt(rr_new) <= cg_tol) {
-        ++it;
-        break;
-      }
-      c.push(rq_axpby(-1.0, r, rr_new / rr, p, w32, n));
-      rr = rr_new;
     }
     // ---- direction xi = s + tau d (eq. xi)
     if (s_is_mg) c.push(rq_axpby(-1.0, B[B_GW], 0.0, xi, w32, n));
