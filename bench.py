@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--batch-solve", action="store_true",
                     help="also time the lock-step batched solve of the 64 problems against one-by-one solves")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="only reproduce the ARNT rows of the Sec. 7.1 tables (every magnetization, R1/R2/R3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -305,6 +307,39 @@ def batch_measure(count, steps, solve, log):
     return out
 
 
+def paper_tables(log):
+    """ARNT on the Sec. 7.1 workloads (Tables 1-1-2 .. 1-3-3): every printed
+    magnetization with the three retractions, FP64, one mesh, ||grad|| <= 1e-6,
+    the paper's initial data.  Energies against the printed ones; times are this
+    GPU's (the paper's: MATLAB on a 12-core Xeon, all meshes)."""
+    import torch
+    from paper_1907_01194_amd import workloads as W
+    from paper_1907_01194_amd.binding import Problem
+    rows = []
+    for table, t in W.PAPER_TABLES.items():
+        for M, E_paper in t["E"].items():
+            spec, X0 = W.paper_table_case(table, M)
+            for retr in (1, 2, 3):
+                gp = Problem(spec, "fp64")
+                X = torch.from_numpy(X0).cuda()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = gp.newton_solve(X, check=False, tol=1e-6, retraction=retr, time_limit=120.0)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                gp.close()
+                del X
+                torch.cuda.empty_cache()
+                inner = st["cg_total"] / max(st["outer"], 1)
+                rows.append({"table": table, "M": M, "retraction": "R%d" % retr, "E": st["E"], "E_paper": E_paper,
+                             "dE": st["E"] - E_paper, "gnorm": st["gnorm"], "converged": bool(st["converged"]),
+                             "outer": st["outer"], "avg_inner": round(inner, 1), "rgbb_iters": st["rgbb_iters"],
+                             "seconds": round(dt, 3)})
+                log("table %s M=%g R%d: E=%.6f (paper %.4f, diff %+.1e) |g|=%.1e iter %d (%.0f) %.2fs" % (
+                    table, M, retr, st["E"], E_paper, st["E"] - E_paper, st["gnorm"], st["outer"], inner, dt))
+    return rows
+
+
 def cpu_baseline(spec, w, noise, log):
     """The oracle (FP64, NumPy/scipy) per Riemannian HVP on the same workload."""
     here = os.path.dirname(os.path.abspath(__file__))
@@ -343,6 +378,10 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(log)
+        return
+    if args.paper_tables:
+        rows = paper_tables(log)
+        print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6}), flush=True)
         return
     from paper_1907_01194_amd import workloads as W
     spec = W.spin3_3d(args.n)

@@ -109,3 +109,19 @@ def test_reduction_to_scalar_gpe():
         _, st = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-9))
         Es.append(st.E)
     assert max(Es) - min(Es) <= 1e-10 * Es[0]
+
+
+def test_table1_1_2_decides_the_lattice_period():
+    """Sec. 7.1, spin-1 2D (Table 1-1-2, M = 0.2, printed 15.1411): the printed
+    potential has sin^2(pi x / 4); the table's energy is that of sin^2(pi x / 2).
+    128^2 on [-16,16]^2 already resolves the energy to the printed digits."""
+    def solve(k):
+        spec = W.make_spec("t112", 1, (128, 128), (-16, -16), (16, 16), W._lat(10.0, k), (300, 100), 0.2)
+        X0 = W.paper_initial(spec, W.paper_U(1, "antiferro", 0.2))
+        _, st = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-6))
+        assert st.converged
+        return st.E
+    assert abs(solve(np.pi / 2) - 15.1411) <= 5e-5
+    assert abs(solve(np.pi / 4) - 15.1411) > 0.3
+    x = np.array([0.5])
+    assert abs(W.PAPER_TABLES["1-1-2"]["V"](x, x)[0] - (0.25 + 20 * np.sin(np.pi / 4) ** 2)) < 1e-14
