@@ -32,7 +32,10 @@ gradient norm; and when the predicted decrease |<grad, xi>| is itself below
 16 eps |E| the Armijo search (whose model values are then rounding noise) is
 skipped and the full step alpha0 xi is tried; that trial has no model value,
 so unless its energy change is also below 16 eps |E| (the gradient-norm rule
-above) it is accepted if and only if the energy decreases.  Thirty rejections
+above) it is accepted if and only if the energy decreases.  A trial step whose
+point u + t xi lies outside the retraction's domain (Omega for R1 and R2, S for
+R3, Sec. 6) counts as a failed trial of its line search (t is reduced); RGBB
+ends if no trial of a search can be retracted.  Thirty rejections
 in a row end
 the run unconverged.  sigma_hat never drops below 1e-8 (repeated very
 successful steps would otherwise drive it to underflow, after which the
@@ -100,6 +103,14 @@ def energy_grad(prob, X):
     return energy(prob, X, LX), egrad(prob, X, LX)
 
 
+def _try_retract(prob, u, xi, t, kind):
+    """R_u(t xi), or None when u + t xi lies outside the retraction's domain."""
+    try:
+        return retract(prob, u, xi, t, kind)
+    except ValueError:
+        return None
+
+
 def rgbb(prob, u, opts, stats):
     """Riemannian gradient method with BB step and nonmonotone search (eq. NMN)."""
     E, G = energy_grad(prob, u)
@@ -113,13 +124,20 @@ def rgbb(prob, u, opts, stats):
         eta = -gR
         slope = inner(gR, eta)
         t = step
+        z = None
         for _ in range(opts.ls_max):
-            z = retract(prob, u, eta, t, opts.retraction)
-            Ez = energy(prob, z)
             stats.ls_trials += 1
+            zt = _try_retract(prob, u, eta, t, opts.retraction)
+            if zt is None:                      # outside the retraction's domain: a failed trial
+                t *= opts.rgbb_delta
+                continue
+            z = zt
+            Ez = energy(prob, z)
             if Ez <= C + opts.rgbb_rho * t * slope:
                 break
             t *= opts.rgbb_delta
+        if z is None:
+            break                               # no trial step could be retracted
         Ez, Gz = energy_grad(prob, z)
         gz = rgrad(prob, z, Gz)[0]
         s = z - u
@@ -195,7 +213,11 @@ def arnt(prob, u, opts, stats):
         # the full step and let the gradient norm decide (reading, see header).
         resolved = abs(slope) > 16 * eps * abs(E)
         for _ in range(opts.ls_max if resolved else 0):
-            z = retract(prob, u, xi, t, opts.retraction)
+            z = _try_retract(prob, u, xi, t, opts.retraction)
+            if z is None:                       # outside the retraction's domain: a failed trial
+                stats.ls_trials += 1
+                t *= opts.delta
+                continue
             dz = z - u
             m = inner(G, dz) + 0.5 * inner(ehvp(prob, u, dz), dz) + 0.5 * sigma * inner(dz, dz)
             stats.hvp_calls += 1
@@ -205,8 +227,8 @@ def arnt(prob, u, opts, stats):
                 break
             t *= opts.delta
         if not resolved:
-            z = retract(prob, u, xi, t, opts.retraction)
-            ok = True
+            z = _try_retract(prob, u, xi, t, opts.retraction)
+            ok = z is not None
             m = 0.0
         ratio = -np.inf
         if ok:

@@ -23,6 +23,9 @@
 //     the full step is tried, and if its energy change is resolved it is
 //     accepted iff the energy decreases; 30 rejections in a row end the run
 //     (each multiplies sigma by 10: by then a trial is a short gradient step);
+//   * a trial step whose point lies outside the retraction's domain (Omega
+//     for R1/R2, S for R3, Sec. 6) is a failed trial of its line search;
+//     RGBB ends when no trial of a search can be retracted;
 //   * sigma_hat is kept >= sigma_hat_min (1e-8): a run of very successful
 //     steps would otherwise drive it to underflow, and the x10 increases on
 //     rejection could then never restore any regularisation.
@@ -285,16 +288,24 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
       ROUND;
       CO_TRY(norms_read(h, true, &rn));
       double t = step, Ez = 0, agz = 0, bgz = 0;
+      bool have_z = false;
       for (int ls = 0; ls < o->ls_max; ++ls) {
-        CO_TRY(retract_sigma_at(h, rn, -t, o->retraction, sig));
+        st->ls_trials++;
+        const gpe_status rs = retract_sigma_at(h, rn, -t, o->retraction, sig);
+        if (rs == GPE_EDOMAIN) {          // outside the retraction's domain: a failed trial
+          t *= o->rgbb_delta;
+          continue;
+        }
+        CO_TRY(rs);
         c.push(rq_scale(u, gR, false, -t, sig, B[B_Z]));
         c.push(rq_eval(B[B_Z], B[B_GZ], h->gram_tmp));
         ROUND;
         CO_TRY(eval_read(h, true, &Ez, &agz, &bgz));
-        st->ls_trials++;
+        have_z = true;
         if (Ez <= C - o->rgbb_rho * t * gn * gn) break;
         t *= o->rgbb_delta;
       }
+      if (!have_z) break;                 // no trial step could be retracted
       double gnz;
       c.push(rq_pgrad(B[B_Z], B[B_GZ], B[B_GRZ], agz, bgz));
       ROUND;
@@ -411,7 +422,13 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     double t = o->alpha0, m = 0;
     bool ok = false;
     for (int ls = 0; resolved && ls < o->ls_max; ++ls) {
-      CO_TRY(retract_sigma_at(h, rn, t, o->retraction, sig));
+      const gpe_status rs = retract_sigma_at(h, rn, t, o->retraction, sig);
+      if (rs == GPE_EDOMAIN) {            // outside the retraction's domain: a failed trial
+        st->ls_trials++;
+        t *= o->delta;
+        continue;
+      }
+      CO_TRY(rs);
       c.push(rq_scale(u, xi, w32, t, sig, B[B_Z]));
       c.push(rq_diff(B[B_Z], u, B[B_DZ], w32, n));
       c.push(rq_hvp(B[B_DZ], B[B_HDZ], false, 0.0, w32));
@@ -431,9 +448,12 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
       t *= o->delta;
     }
     if (!resolved) {
-      CO_TRY(retract_sigma_at(h, rn, t, o->retraction, sig));
-      c.push(rq_scale(u, xi, w32, t, sig, B[B_Z]));
-      ok = true;
+      const gpe_status rs = retract_sigma_at(h, rn, t, o->retraction, sig);
+      if (rs != GPE_EDOMAIN) {
+        CO_TRY(rs);
+        c.push(rq_scale(u, xi, w32, t, sig, B[B_Z]));
+        ok = true;
+      }
       m = 0.0;
     }
     double ratio = -INFINITY, Ez = 0, agz = 0, bgz = 0, gnz = -1.0;

@@ -125,3 +125,16 @@ def test_table1_1_2_decides_the_lattice_period():
     assert abs(solve(np.pi / 4) - 15.1411) > 0.3
     x = np.array([0.5])
     assert abs(W.PAPER_TABLES["1-1-2"]["V"](x, x)[0] - (0.25 + 20 * np.sin(np.pi / 4) ** 2)) < 1e-14
+
+
+@pytest.mark.slow
+def test_closed_form_retraction_outside_S_is_a_failed_trial():
+    """Sec. 6.3: the closed-form retraction is defined on S only.  On the spin-3
+    2D workload of Table 1-3-2 (32^2 here) early RGBB and Armijo trials leave S;
+    they count as failed trials, and R3 reaches the minimizer R1 reaches."""
+    spec, X0 = W.paper_table_case("1-3-2", 0.5, n=32)
+    prob = oracle_problem(spec)
+    _, s3 = oracle.solve(prob, X0, oracle.SolveOpts(tol=1e-6, retraction=3))
+    _, s1 = oracle.solve(prob, X0, oracle.SolveOpts(tol=1e-6, retraction=1))
+    assert s3.converged and s1.converged
+    assert abs(s3.E - s1.E) <= 1e-10 * abs(s1.E)
