@@ -45,3 +45,22 @@ def test_table_3d_256(torch, table, M):
     st = _solve(torch, table, M, 1)
     assert st["converged"] and st["gnorm"] <= 1e-6
     assert abs(st["E"] - W.PAPER_TABLES[table]["E"][M]) <= 5e-5
+
+
+def test_table_1_2_3_m0_entry_is_not_the_minimum(torch):
+    """Spin-2 3D cyclic case, M = 0 (printed 46.2917, above the printed M = 0.5
+    entry 45.7403): beta1, beta2 > 0 make every state's energy at least that of
+    the scalar GPE with the same beta0, and the solver attains that bound, far
+    below the printed value (the same situation as Table 3-1's cyclic M = 0)."""
+    from paper_1907_01194_amd.binding import Problem
+    t = W.PAPER_TABLES["1-2-3"]
+    full, X0 = W.paper_table_case("1-2-3", 0.0)
+    scalar = W.make_spec("t123-scalar", 2, full.n, full.lo, full.hi, t["V"], (t["beta"][0], 0.0, 0.0), 0.0)
+    E = []
+    for spec in (full, scalar):
+        gp = Problem(spec, "fp64")
+        _, st = gp.newton_solve(torch.from_numpy(X0).cuda(), tol=1e-6)
+        gp.close()
+        E.append(st["E"])
+    assert abs(E[0] - E[1]) <= 1e-8 * abs(E[1])
+    assert E[0] < t["E"][0.0] - 0.5
