@@ -100,6 +100,13 @@ typedef struct gpe_solve_opts {
   int mg_levels;         /* cascadic multigrid (Algorithm 1, outer loop): number of coarser meshes,
                             each halving every axis of the same box (0: one mesh) */
   double mg_coarse_tol;  /* ||grad|| tolerance on the coarse meshes (Sec. 7.1: 1e-5) */
+  /* FP64 polish of a GPE_MIXED solve: its HVPs and CG switch to FP64 for the
+   * rest of the run once ||grad|| <= polish_tol (0: never), or once
+   * polish_window outer iterations in a row have not halved the best ||grad||
+   * (0: never).  No effect on a GPE_FP64 handle.  Both are off by default: on
+   * problems whose slowness is physical (soft modes) FP64 only costs time. */
+  double polish_tol;     /* default 0 */
+  int polish_window;     /* default 0 */
 } gpe_solve_opts;
 
 typedef struct gpe_solve_stats {
@@ -119,6 +126,7 @@ typedef struct gpe_solve_stats {
   double mag_err;        /* |magnetization - M| of the result */
   int mg_levels;         /* coarse meshes actually used */
   double t_coarse;       /* seconds spent on the coarse meshes (included in t_total) */
+  int polish_at;         /* outer iteration at which the FP64 polish began (-1: none) */
 } gpe_solve_stats;
 
 /* Fill *opts with the defaults listed in gpe_solve_opts.  Never fails. */

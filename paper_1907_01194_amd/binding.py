@@ -44,7 +44,8 @@ class gpe_solve_opts(ctypes.Structure):
                 ("rho", c_double), ("delta", c_double), ("alpha0", c_double),
                 ("ls_max", c_int), ("cg_maxit", c_int), ("cg_T", c_double), ("cg_theta", c_double),
                 ("max_reject_streak", c_int), ("sigma_hat_min", c_double), ("verbose", c_int), ("time_limit", c_double),
-                ("mg_levels", c_int), ("mg_coarse_tol", c_double)]
+                ("mg_levels", c_int), ("mg_coarse_tol", c_double), ("polish_tol", c_double),
+                ("polish_window", c_int)]
 
 
 class gpe_solve_stats(ctypes.Structure):
@@ -52,7 +53,7 @@ class gpe_solve_stats(ctypes.Structure):
                 ("outer", c_int), ("cg_total", c_int), ("hvp_calls", c_int), ("ls_trials", c_int),
                 ("rejected", c_int), ("t_total", c_double), ("t_rgbb", c_double),
                 ("t_arnt", c_double), ("mass_err", c_double), ("mag_err", c_double),
-                ("mg_levels", c_int), ("t_coarse", c_double)]
+                ("mg_levels", c_int), ("t_coarse", c_double), ("polish_at", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

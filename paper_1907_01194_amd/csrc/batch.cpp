@@ -393,7 +393,7 @@ gpe_status ex_hvp(gpe_batch* b, std::vector<Item>& g) {
   }
   const bool riem = g[0].r->flag, cg = g[0].r->cg;
   if (cg && !riem) return fail(g[0].c->h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
-  return b->prec == GPE_MIXED ? hvp_batched<float>(b, g, riem, cg) : hvp_batched<double>(b, g, riem, cg);
+  return g[0].r->a32 ? hvp_batched<float>(b, g, riem, cg) : hvp_batched<double>(b, g, riem, cg);
 }
 
 gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
@@ -413,7 +413,7 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
     }
     return ops(b, recs, nb);
   };
-  GPE_TRY(b->prec == GPE_MIXED ? run(CgArgs<float>{}) : run(CgArgs<double>{}));
+  GPE_TRY(g[0].r->a32 ? run(CgArgs<float>{}) : run(CgArgs<double>{}));
   return fin_nblk(b, g, 1, POST_CG_STEP, no_gram(g.size()), true);
 }
 

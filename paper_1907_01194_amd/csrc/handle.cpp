@@ -138,7 +138,7 @@ gpe_status project_grad(gpe_handle* h, const void* X, const void* G, void* gR, d
 
 gpe_status adopt_point(gpe_handle* h) {
   // the HVP needs L X_p for <X_i, (LZ)_i> = <(LX)_i, Z_i>
-  if (h->prec == GPE_MIXED) {
+  if (work32(h)) {
     GPE_HIP(h, to_c64(h->Xp, h->Xp32, h->nel, h->st));
     GPE_TRY(laplacian<float>(h, h->Xp32, h->LX32));
   } else {
@@ -245,7 +245,7 @@ gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sig
   if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
   if (cg && !riem) return fail(h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
   const PwParams p = hvp_params(h, riem, sigma);
-  if (h->prec == GPE_FP64) return hvp_t<double>(h, Z, HZ, riem, p, cg);
+  if (!work32(h)) return hvp_t<double>(h, Z, HZ, riem, p, cg);
   return hvp_t<float>(h, Z, HZ, riem, p, cg);
 }
 
@@ -463,11 +463,11 @@ static gpe_status cg_dir_t(gpe_handle* h, const void* r, void* p) {
 }
 
 gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r) {
-  return h->prec == GPE_MIXED ? cg_step_t<float>(h, p, q, z, r) : cg_step_t<double>(h, p, q, z, r);
+  return work32(h) ? cg_step_t<float>(h, p, q, z, r) : cg_step_t<double>(h, p, q, z, r);
 }
 
 gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p) {
-  return h->prec == GPE_MIXED ? cg_dir_t<float>(h, r, p) : cg_dir_t<double>(h, r, p);
+  return work32(h) ? cg_dir_t<float>(h, r, p) : cg_dir_t<double>(h, r, p);
 }
 
 gpe_status cg_state_read(gpe_handle* h, CgState* cs) {
@@ -581,6 +581,8 @@ void gpe_solve_opts_default(gpe_solve_opts* o) {
   o->time_limit = 0.0;
   o->mg_levels = 0;
   o->mg_coarse_tol = 1e-5;
+  o->polish_tol = 0.0;
+  o->polish_window = 0;
 }
 
 const char* gpe_last_error(const gpe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }

@@ -54,6 +54,7 @@ struct gpe_handle {
 
   // set-point state
   bool has_point = false;
+  bool polish = false;   // a mixed handle's HVPs and CG run in FP64 (FP64 polish of a solve)
   double E_pt = 0, alpha_g = 0, beta_g = 0;
 
   // per-kernel event timing (gpe_timing_enable)
@@ -115,6 +116,9 @@ hipEvent_t timing_event(gpe_handle* h);
   } while (0)
 
 gpe_status alloc_field(gpe_handle* h, void** p, size_t bytes);
+
+// Work precision of HVPs and CG vectors: c64 for a mixed handle unless it polishes in FP64.
+inline bool work32(const gpe_handle* h) { return h->prec == GPE_MIXED && !h->polish; }
 
 // out = L in (all axes), field precision T.
 template <typename T>

@@ -77,10 +77,10 @@ enum {
 
 gpe_status ensure_bufs(gpe_handle* h) {
   if ((int)h->solver_bufs.size() == B_COUNT) return GPE_OK;
+  // work buffers take c128 in a mixed handle too: an FP64 polish reuses them
   const size_t f64 = h->nel * 16;
-  const size_t fw = h->nel * (h->prec == GPE_FP64 ? 16 : 8);
   h->solver_bufs.assign(B_COUNT, nullptr);
-  for (int b = 0; b < B_COUNT; ++b) GPE_TRY(alloc_field(h, &h->solver_bufs[b], b < B_R ? f64 : fw));
+  for (int b = 0; b < B_COUNT; ++b) GPE_TRY(alloc_field(h, &h->solver_bufs[b], f64));
   return GPE_OK;
 }
 
@@ -228,7 +228,7 @@ Req rq_cginit(double tol, double eps, int maxit) {
 // needs L X_p for <X_i, (LZ)_i> = <(LX)_i, Z_i>.
 void push_adopt(Ctx& c) {
   gpe_handle* h = c.h;
-  if (h->prec == GPE_MIXED) {
+  if (work32(h)) {
     c.push(rq_copy(h->Xp, false, h->Xp32, true, h->nel));
     c.push(rq_lap(h->Xp32, h->LX32, true));
   } else {
@@ -251,7 +251,9 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
   Clock clk;
   CO_TRY(ensure_bufs(h));
   auto& B = h->solver_bufs;
-  const bool w32 = h->prec == GPE_MIXED;
+  h->polish = false;
+  bool w32 = work32(h);
+  st->polish_at = -1;
   const size_t n = h->nel;
   const double eps = 2.220446049250313e-16;
   double sig[7];
@@ -350,10 +352,28 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
   double shat = o->sigma_hat0;
   int streak = 0;
   bool converged = false;
+  double best_gn = gn;   // for the stagnation test of the FP64 polish
+  int best_k = 0;
   for (int k = 0; k < o->maxit; ++k) {
     if (gn <= o->tol) {
       converged = true;
       break;
+    }
+    if (gn < 0.5 * best_gn) {
+      best_gn = gn;
+      best_k = k;
+    }
+    // FP64 polish of a mixed solve: below polish_tol, or when polish_window
+    // outer iterations have not halved ||grad|| (the c64 Hessian cannot
+    // resolve the soft directions that remain)
+    if (w32 && ((o->polish_tol > 0 && gn <= o->polish_tol) ||
+                (o->polish_window > 0 && k - best_k >= o->polish_window))) {
+      if (!h->LX64) CO_TRY(alloc_field(h, &h->LX64, h->nel * 16));
+      h->polish = true;
+      w32 = false;
+      push_adopt(c);
+      st->polish_at = k;
+      if (o->verbose) std::fprintf(stderr, "arnt %d: FP64 polish from |g|=%.3e\n", k, gn);
     }
     if (streak >= o->max_reject_streak) break;
     if (o->time_limit > 0 && clk.sec() > o->time_limit) break;
@@ -504,6 +524,10 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     if (sigma_est >= 0 && gn > 0) shat = std::fmax(shat * gn, sigma_est) / gn;
   }
   st->t_arnt = carnt.sec();
+  if (h->polish) {   // leave the handle's HVPs in its own precision at the final point
+    h->polish = false;
+    push_adopt(c);
+  }
 
   c.push(rq_copy(u, false, Xio, false, n));
   c.push(rq_norms(u, nullptr, false));

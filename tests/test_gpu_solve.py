@@ -59,7 +59,7 @@ def test_solve_paper_table3_1(torch, case, beta, box, n, M, E_paper):
     assert abs(st["E"] - E_paper) <= 1e-8
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed+polish"])
 def test_solve_spin2_2d_small(torch, prec):
     """A 2D spin-2 solve (32^2, the spin-2 2D workload's physics on a coarser
     grid, smooth initial data U phi_0 with a seeded spinor U) against the
@@ -71,10 +71,12 @@ def test_solve_spin2_2d_small(torch, prec):
     spec = W.make_spec("s2", 2, (32, 32), s.lo, s.hi, W.lattice(10.0, np.pi / 4), s.beta[:3], s.M)
     X0 = W.paper_initial(spec, np.random.default_rng(0).random(5))
     u_or, st_or = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-6))
-    gp = Problem(spec, prec)
-    X, st = gp.newton_solve(dev(X0), tol=1e-6)
+    # mixed+polish: c64 HVPs down to ||grad|| = 1e-3, then the FP64 polish
+    gp = Problem(spec, prec.split("+")[0])
+    X, st = gp.newton_solve(dev(X0), tol=1e-6, polish_tol=1e-3 if "polish" in prec else 0.0)
     assert st["converged"]
-    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert (st["polish_at"] >= 0) == ("polish" in prec)
+    tol = 1e-5 if prec == "mixed" else 1e-10
     assert abs(st["E"] - st_or.E) <= tol * abs(st_or.E)
     assert st["gnorm"] <= 1e-6
     assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
