@@ -11,7 +11,7 @@ namespace gpe {
 // One block per slot sums that slot's partials in a fixed order (so results
 // are bitwise reproducible); the last block to finish (counted with an atomic
 // ticket, which it resets) applies the post-operation.
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 1024;   // up to 16k partials per slot: 16 loads per thread
 
 __device__ void finalize_body(const double* __restrict__ part, size_t stride, const SlotCounts& nb, int nq,
                               double* __restrict__ res, int post, int F, double* gram, unsigned int* ticket, int q,
