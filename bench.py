@@ -125,10 +125,11 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log):
     for _ in range(warmup):
         gp.hvp_dot(Z, 1e-2, out=HZ)
     torch.cuda.synchronize()
+    # the handle runs on torch's current stream, so these events bracket its work
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    gp.timing(True)
+    # (1) the timed region: `steps` HVPs, nothing else on the stream
     e0.record(stream)
     t0 = time.perf_counter()
     kappa = 0.0
@@ -138,11 +139,18 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
+    # (2) the same HVPs again with the library's HIP events around every launch
+    # (on the handle's stream): per-kernel durations for the breakdown and the roofline
+    gp.timing(True)
+    for _ in range(steps):
+        gp.hvp_dot(Z, 1e-2, out=HZ)
+    torch.cuda.synchronize()
     kt = gp.timing_read()
     gp.timing(False)
     sched = gp.schedule()
     log("%s: x-pass schedule variant %d (autotuned; us per variant %s)" % (prec, sched[0], sched[1]))
-    log("%s: %.1f us per HVP (events), %.1f us (wall), kappa=%.6e" % (prec, 1e3 * ms, 1e6 * wall / steps, kappa))
+    log("%s: %.1f us per HVP (events), %.1f us (wall), kappa=%.6e; per-kernel pass (events around each launch):"
+        % (prec, 1e3 * ms, 1e6 * wall / steps, kappa))
     for k, (c, t) in sorted(kt.items(), key=lambda x: -x[1][1]):
         log("   %-12s %6d launches  %9.1f us avg" % (k, c, 1e3 * t / c))
     del gp
