@@ -130,3 +130,32 @@ def test_batch_rejects_unsupported(torch):
     other = W.spin2_2d()
     with pytest.raises(GpeError):
         Batch(specs + [other], "mixed")
+
+
+@pytest.mark.parametrize("F,dim,sizes", [(2, 3, (16, 32)), (3, 2, (32, 64)), (1, 1, (64, 128))])
+def test_batch_hvp_other_spins_and_dims(torch, F, dim, sizes):
+    """Batched HVPs (FP64, Riemannian and Euclidean) for spin-2 3D, spin-3 2D and
+    spin-1 1D batches of uneven grids against the single-problem HVP."""
+    from paper_1907_01194_amd.binding import Batch
+    from gpu_util import host
+    beta = {1: (100, -0.5), 2: (100, 1, -1), 3: (100, 1, 10, 1)}[F]
+    rng = np.random.default_rng(F * 10 + dim)
+    specs = []
+    for i in range(5):
+        n = int(sizes[i % len(sizes)])
+        specs.append(W.make_spec("b%d" % i, F, (n,) * dim, (-8.0,) * dim, (8.0,) * dim, W.lattice(10.0, np.pi / 2),
+                                 beta, float(rng.uniform(0.1, 0.5))))
+    print("batch hvp F=%d dim=%d" % (F, dim), [s.n for s in specs], flush=True)
+    b = Batch(specs, "fp64")
+    pts, dirs = _points(b, specs, 300)
+    for p, X in zip(b.problems, pts):
+        p.set_point(X)
+    sig = [0.05] * len(specs)
+    for riem in (True, False):
+        HB, kap = b.hvp(dirs, riemannian=riem, sigma=sig)
+        for i, p in enumerate(b.problems):
+            HS, k1 = p.hvp_dot(dirs[i], sigma=sig[i]) if riem else (p.hvp(dirs[i]), None)
+            assert rel(host(HB[i]), host(HS)) <= 1e-12, (i, riem)
+            if riem:
+                assert abs(kap[i] - k1) <= 1e-12 * max(abs(k1), 1.0)
+    b.close()
