@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--paper-tables", action="store_true",
                     help="only reproduce the ARNT rows of the Sec. 7.1 tables (every magnetization, R1/R2/R3)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the paper's spin-3 128^3 ground-state solve (for profiling the whole solve)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -372,6 +374,22 @@ def cpu_baseline(spec, w, noise, log):
                       "scipy.fft workers=%d" % (reps, os.cpu_count())}
 
 
+def paper_case_solves(n, precs, log):
+    """The paper's spin-3 128^3 workload (Sec. 7.3 Table 4-1 3D / Table 1-3-3, Case II, M = 0.5)
+    from the paper's initial data, solved to ||grad|| <= 1e-6 in each precision."""
+    from paper_1907_01194_amd import workloads as W
+    ps = W.spin3_3d_paper(n, "II", 0.5)
+    pw = W.paper_initial(ps, W.paper_U(3, None, ps.M, 0))
+    entry = {"workload": ps.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
+             "paper_energy": 42.9822,
+             "paper_context": {"seconds": 1050.1, "hardware": "MATLAB R2018b, 12-core Xeon E5-2680 v3",
+                               "source": "Sec. 7.1 Table 1-3-3, ARNT with R1, M = 0.5, all meshes"}}
+    for prec in precs:
+        entry[prec] = time_solve(ps, prec, pw, 300.0, log)
+        entry[prec]["energy_err_vs_paper"] = abs(entry[prec]["E"] - 42.9822)
+    return entry
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -392,10 +410,13 @@ def main():
         print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6}), flush=True)
         return
     from paper_1907_01194_amd import workloads as W
+    precs = args.precisions.split(",")
+    if args.solve_only:
+        print(json.dumps({"time_to_ground_state": {"paper_case": paper_case_solves(args.n, precs, log)}}), flush=True)
+        return
     spec = W.spin3_3d(args.n)
     w = W.initial_state(spec, 3)
     noise = W.random_direction(spec, 103)
-    precs = args.precisions.split(",")
     res = {}
     for prec in precs:
         ms, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
@@ -404,18 +425,7 @@ def main():
                      "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]}}
     solves = {}
     if not args.no_solve:
-        # (a) the paper's spin-3 128^3 workload (Sec. 7.3 Table 4-1 3D / Table 1-3-3,
-        #     Case II, M = 0.5) from the paper's initial data: converges
-        ps = W.spin3_3d_paper(args.n, "II", 0.5)
-        pw = W.paper_initial(ps, W.paper_U(3, None, ps.M, 0))
-        entry = {"workload": ps.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
-                 "paper_energy": 42.9822,
-                 "paper_context": {"seconds": 1050.1, "hardware": "MATLAB R2018b, 12-core Xeon E5-2680 v3",
-                                   "source": "Sec. 7.1 Table 1-3-3, ARNT with R1, M = 0.5, all meshes"}}
-        for prec in precs:
-            entry[prec] = time_solve(ps, prec, pw, 300.0, log)
-            entry[prec]["energy_err_vs_paper"] = abs(entry[prec]["E"] - 42.9822)
-        solves["paper_case"] = entry
+        solves["paper_case"] = paper_case_solves(args.n, precs, log)
         # (b) the benchmark physics (beta = (500, 5, -5, 2), gamma = (1, 1, 2)) from the same
         #     kind of initial data, capped: its soft modes make the Newton iteration slow
         bw = W.paper_initial(spec, W.paper_U(3, None, spec.M, 3))
