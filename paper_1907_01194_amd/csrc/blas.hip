@@ -284,7 +284,9 @@ __device__ void run_op(const CgArgs<T>& a, int blk, int nblk) {
   auto r = reinterpret_cast<c_t<T>*>(a.r);
   const T ca = (T)(a.adev ? *a.adev : a.a);
   double acc[1] = {0.0};
-  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
+  // last element first: the HVP before this update ends on the last component
+  for (size_t f = (size_t)blk * blockDim.x + threadIdx.x; f < a.n; f += (size_t)nblk * blockDim.x) {
+    const size_t e = a.n - 1 - f;
     const c_t<T> pv = p[e], qv = q[e];
     c_t<T> zv = z[e], rv = r[e];
     zv.x += ca * pv.x;

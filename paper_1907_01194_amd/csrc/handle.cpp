@@ -177,7 +177,7 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
       const bool proj = riem && a == h->dim - 1;
       GPE_KT(h, KK_LAP_X + a,
              lap_axis_ex<T>(h->ax[a], Z, HZ, HZ, h->F, h->npts, proj ? Xw : nullptr, coef, h->part, h->pstride,
-                            6 + a, &nb.nb[6 + a], skip, h->st));
+                            6 + a, &nb.nb[6 + a], skip, a == 1, h->st));
       nq = 7 + a;
     }
   }

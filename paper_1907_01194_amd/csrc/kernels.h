@@ -66,7 +66,7 @@ int xpass_variants(int n);
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nblk_out,
-                       const double* skip, hipStream_t st);
+                       const double* skip, int rev, hipStream_t st);
 size_t lap_max_blocks(const LapAxis& ax, int K);
 
 // Post-processing done by the single-block finalize kernel after summing the
