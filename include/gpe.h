@@ -91,7 +91,7 @@ typedef struct gpe_solve_opts {
   double eta1, eta2, gamma0, gamma1, gamma2, sigma_hat0;  /* 0.01 0.9 0.2 1 10 1 */
   double rho, delta, alpha0;   /* Armijo on the model: 1e-4, 0.2, 1 */
   int ls_max;            /* backtracks per search (30) */
-  int cg_maxit;          /* truncated-CG iterations per subproblem (500) */
+  int cg_maxit;          /* most truncated-CG iterations per subproblem (500) */
   double cg_T, cg_theta; /* CG stop ||r|| <= min(T, ||g||^theta) ||g|| (0.1, 1) */
   int max_reject_streak; /* consecutive ARNT rejections that end the run (30) */
   double sigma_hat_min;  /* lower bound of sigma_hat (1e-8) */
@@ -107,6 +107,11 @@ typedef struct gpe_solve_opts {
    * problems whose slowness is physical (soft modes) FP64 only costs time. */
   double polish_tol;     /* default 0 */
   int polish_window;     /* default 0 */
+  /* Cap of subproblem k's truncated CG chosen from ||grad|| (Sec. 7.1 says it is
+   * adaptive in ||grad|| and leaves the rule open): min(cg_maxit,
+   * ceil(cg_per_digit * log10(1 / min(T, ||g||^theta)))), a number of iterations
+   * per decimal digit the CG residual must gain (80; 0: the fixed cap cg_maxit). */
+  double cg_per_digit;
 } gpe_solve_opts;
 
 typedef struct gpe_solve_stats {

@@ -25,7 +25,10 @@ alpha0 = 1, rho = 1e-4, delta = 0.2, at most 30 backtracks.  sigma_hat is
 multiplied by gamma0 = 0.2 when rho_k >= eta2, by gamma1 = 1 when
 eta1 <= rho_k < eta2, by gamma2 = 10 on rejection.  RGBB: rho = 1e-4,
 delta = 0.2, varrho = 0.85, first step 0.1/||grad||, BB step clamped to
-[1e-20, 1e20].  Inner iterations capped at 500.  When both the energy change
+[1e-20, 1e20].  The inner iterations of a subproblem are capped, as Sec. 7.1
+says, by a rule in ||grad||: 80 iterations per decimal digit the CG residual
+must gain, ceil(80 log10(1 / min(T, ||g||^theta))), and never more than 500.
+When both the energy change
 and the model value are below 16 eps |E| neither can rank the two points: the
 trial is then accepted (ratio 1) if and only if it lowers the Riemannian
 gradient norm; and when the predicted decrease |<grad, xi>| is itself below
@@ -74,6 +77,7 @@ class SolveOpts:
     alpha0: float = 1.0
     ls_max: int = 30
     cg_maxit: int = 500
+    cg_per_digit: float = 80.0   # 0: the fixed cap cg_maxit
     cg_T: float = 0.1
     cg_theta: float = 1.0
     sigma_hat_min: float = 1e-8
@@ -162,7 +166,11 @@ def tcg(prob, u, gR, ag, bg, sigma, opts, stats):
     r = gR.copy()
     p = -r
     rr = inner(r, r)
-    for i in range(opts.cg_maxit):
+    cap = opts.cg_maxit
+    if opts.cg_per_digit > 0:
+        digits = np.log10(1.0 / min(opts.cg_T, gn ** opts.cg_theta))
+        cap = int(min(opts.cg_maxit, max(1.0, np.ceil(opts.cg_per_digit * digits))))
+    for i in range(cap):
         Ap = rhess(prob, u, p, ag, bg, sigma)
         stats.hvp_calls += 1
         stats.cg_total += 1

@@ -45,7 +45,7 @@ class gpe_solve_opts(ctypes.Structure):
                 ("ls_max", c_int), ("cg_maxit", c_int), ("cg_T", c_double), ("cg_theta", c_double),
                 ("max_reject_streak", c_int), ("sigma_hat_min", c_double), ("verbose", c_int), ("time_limit", c_double),
                 ("mg_levels", c_int), ("mg_coarse_tol", c_double), ("polish_tol", c_double),
-                ("polish_window", c_int)]
+                ("polish_window", c_int), ("cg_per_digit", c_double)]
 
 
 class gpe_solve_stats(ctypes.Structure):

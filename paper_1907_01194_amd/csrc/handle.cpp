@@ -583,6 +583,7 @@ void gpe_solve_opts_default(gpe_solve_opts* o) {
   o->mg_coarse_tol = 1e-5;
   o->polish_tol = 0.0;
   o->polish_window = 0;
+  o->cg_per_digit = 80.0;
 }
 
 const char* gpe_last_error(const gpe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }

@@ -394,7 +394,12 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     c.push(rq_dot(r, w32, r, w32, n));
     const double cg_tol = std::fmin(o->cg_T, std::pow(gn, o->cg_theta)) * gn;
     const double eps_c = 1e-12 * std::fmax(1.0, gn);
-    c.push(rq_cginit(cg_tol, eps_c, o->cg_maxit));
+    int cg_cap = o->cg_maxit;
+    if (o->cg_per_digit > 0) {
+      const double digits = std::log10(1.0 / std::fmin(o->cg_T, std::pow(gn, o->cg_theta)));
+      cg_cap = (int)std::fmin((double)o->cg_maxit, std::fmax(1.0, std::ceil(o->cg_per_digit * digits)));
+    }
+    c.push(rq_cginit(cg_tol, eps_c, cg_cap));
     CgState cs{};
     for (int kstep = 2;; kstep = std::min(2 * kstep, 16)) {
       for (int j = 0; j < kstep; ++j) push_cg_iteration(c, p, Ap, cz, r, sigma, w32);
