@@ -157,6 +157,16 @@ def rgbb(prob, u, opts, stats):
     return u
 
 
+def cg_cap(opts, gn):
+    """Inner-iteration cap of a subproblem at ||grad|| = gn (Sec. 7.1: adaptive in
+    ||grad||; reading: cg_per_digit iterations per decimal digit the residual
+    must gain, at most cg_maxit; cg_per_digit = 0 gives the fixed cap)."""
+    if opts.cg_per_digit <= 0:
+        return opts.cg_maxit
+    digits = np.log10(1.0 / min(opts.cg_T, gn ** opts.cg_theta))
+    return int(min(opts.cg_maxit, max(1.0, np.ceil(opts.cg_per_digit * digits))))
+
+
 def tcg(prob, u, gR, ag, bg, sigma, opts, stats):
     """Truncated CG on Hess m_k[xi] = -grad m_k.  Returns (s, d, A d, sigma_est)."""
     gn = _norm(gR)
@@ -166,11 +176,7 @@ def tcg(prob, u, gR, ag, bg, sigma, opts, stats):
     r = gR.copy()
     p = -r
     rr = inner(r, r)
-    cap = opts.cg_maxit
-    if opts.cg_per_digit > 0:
-        digits = np.log10(1.0 / min(opts.cg_T, gn ** opts.cg_theta))
-        cap = int(min(opts.cg_maxit, max(1.0, np.ceil(opts.cg_per_digit * digits))))
-    for i in range(cap):
+    for i in range(cg_cap(opts, gn)):
         Ap = rhess(prob, u, p, ag, bg, sigma)
         stats.hvp_calls += 1
         stats.cg_total += 1

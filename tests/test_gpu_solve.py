@@ -82,6 +82,23 @@ def test_solve_spin2_2d_small(torch, prec):
     assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
 
 
+def test_solve_fixed_cg_cap_option(torch):
+    """cg_per_digit = 0 restores the fixed truncated-CG cap (cg_maxit): the 2D
+    spin-2 solve reaches the oracle's ground-state energy either way."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev
+    print("solve spin-2 2D 32 fixed CG cap", flush=True)
+    s = W.spin2_2d()
+    spec = W.make_spec("s2", 2, (32, 32), s.lo, s.hi, W.lattice(10.0, np.pi / 4), s.beta[:3], s.M)
+    X0 = W.paper_initial(spec, np.random.default_rng(0).random(5))
+    u_or, st_or = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-6))
+    gp = Problem(spec, "fp64")
+    X, st = gp.newton_solve(dev(X0), tol=1e-6, cg_per_digit=0.0)
+    assert st["converged"]
+    assert abs(st["E"] - st_or.E) <= 1e-10 * abs(st_or.E)
+    assert st["gnorm"] <= 1e-6
+
+
 def _table41_3d(case, M):
     import os
     for line in open(os.path.join(os.path.dirname(__file__), "golden", "table4_1_spin3_3d.txt")):

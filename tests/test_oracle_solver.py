@@ -138,3 +138,28 @@ def test_closed_form_retraction_outside_S_is_a_failed_trial():
     _, s1 = oracle.solve(prob, X0, oracle.SolveOpts(tol=1e-6, retraction=1))
     assert s3.converged and s1.converged
     assert abs(s3.E - s1.E) <= 1e-10 * abs(s1.E)
+
+
+def test_cg_cap_rule():
+    """The truncated CG's cap (Sec. 7.1: chosen from ||grad||): 80 iterations per
+    decimal digit of min(T, ||g||^theta), at most 500; 0 per digit: fixed 500."""
+    from oracle.solver import SolveOpts, cg_cap
+    o = SolveOpts()
+    assert cg_cap(o, 0.5) == 80            # min(T, ||g||) = T = 0.1: one digit
+    assert cg_cap(o, 1e-2) == 160          # two digits
+    assert cg_cap(o, 2e-3) == 216          # log10(500) = 2.699
+    assert cg_cap(o, 1e-6) == 480
+    assert cg_cap(o, 1e-7) == 500          # 560 capped
+    assert cg_cap(SolveOpts(cg_per_digit=0), 0.5) == 500
+    assert cg_cap(SolveOpts(cg_theta=0.5), 1e-4) == 160   # ||g||^theta = 1e-2
+
+
+def test_table3_1_ferro_with_fixed_cg_cap():
+    """The ground state does not depend on the cap rule: with the fixed cap of
+    500 the spin-2 1D ferromagnetic row of Table 3-1 reaches its printed
+    10-digit energy as it does with the per-digit cap."""
+    row = _rows("table3_1_spin2_1d.txt")[0]
+    spec, X0, E = spin2_case(row)
+    _, st = oracle.solve(oracle_problem(spec), X0, oracle.SolveOpts(tol=1e-7, cg_per_digit=0))
+    assert st.converged
+    assert abs(st.E - E) <= 1e-8
