@@ -394,7 +394,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the workload is one spin-3 128^3 grid; "
+        print("bench.py: the benchmark runs on one GPU only (the workload is one spin-3 128^3 grid; "
               "--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     log = lambda m: print(m, file=sys.stderr, flush=True)
