@@ -48,8 +48,8 @@ gpe_status launch_records(gpe_batch* b, const std::vector<A>& recs, const std::v
   }
   const void* da = nullptr;
   const void* db = nullptr;
-  GPE_TRY(b->sg.put(h0, b->st, recs.data(), sizeof(A) * recs.size(), &da));
-  GPE_TRY(b->sg.put(h0, b->st, blk0.data(), sizeof(int) * blk0.size(), &db));
+  GPE_TRY(b->sg.put2(h0, b->st, recs.data(), sizeof(A) * recs.size(), blk0.data(), sizeof(int) * blk0.size(), &da,
+                     &db));
   const Span sp{reinterpret_cast<const int*>(db), (int)recs.size(), blk0.back()};
   GPE_HIP(h0, fn(reinterpret_cast<const A*>(da), sp));
   return GPE_OK;
@@ -472,6 +472,25 @@ gpe_status Stager::put(gpe_handle* h, hipStream_t st, const void* src, size_t by
   std::memcpy(host + off, src, bytes);
   GPE_HIP(h, hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st));
   *dptr = dev + off;
+  off += need;
+  return GPE_OK;
+}
+
+gpe_status Stager::put2(gpe_handle* h, hipStream_t st, const void* a, size_t na, const void* b, size_t nb,
+                        const void** da, const void** db) {
+  const size_t oa = (na + 15) / 16 * 16;
+  const size_t bytes = oa + nb;
+  const size_t need = (bytes + kAlign - 1) / kAlign * kAlign;
+  if (need > cap) return fail(h, GPE_ENOMEM, "batched launch records exceed the staging arena");
+  if (off + need > cap) {
+    GPE_HIP(h, hipStreamSynchronize(st));   // every staged record has been consumed
+    off = 0;
+  }
+  std::memcpy(host + off, a, na);
+  std::memcpy(host + off + oa, b, nb);
+  GPE_HIP(h, hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st));
+  *da = dev + off;
+  *db = dev + off + oa;
   off += need;
   return GPE_OK;
 }

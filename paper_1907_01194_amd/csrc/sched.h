@@ -108,6 +108,10 @@ struct Stager {
   // Copy bytes to the device (stream-ordered) and return the device address.
   // When the arena is full the stream is synchronised and it starts over.
   gpe_status put(gpe_handle* h, hipStream_t st, const void* src, size_t bytes, const void** dptr);
+  // Two arrays staged back to back with one copy: the second starts at the
+  // first's size rounded up to 16 bytes.
+  gpe_status put2(gpe_handle* h, hipStream_t st, const void* a, size_t na, const void* b, size_t nb,
+                  const void** da, const void** db);
 };
 
 // Run queued operations and the rounds of lock-step drivers.
