@@ -60,21 +60,44 @@ gpe_status ops(gpe_batch* b, const std::vector<A>& recs, const std::vector<int>&
   return launch_records(b, recs, nblk, [&](const A* d, const Span& sp) { return launch_batched<A>(d, sp, b->st); });
 }
 
-gpe_status fin(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const std::vector<double*>& gram,
-               const std::vector<SlotCounts>& nb, bool pstride, bool cg = false) {
+// Finalize records of every problem of g (slot counts checked against the stride).
+gpe_status fin_records(gpe_batch* b, const std::vector<Item>& g, int nq, const std::vector<double*>& gram,
+                       const std::vector<SlotCounts>& nb, bool pstride, bool cg, std::vector<FinArgs>* recs) {
   gpe_handle* h0 = b->hs[0];
-  std::vector<FinArgs> recs(g.size());
+  recs->resize(g.size());
   for (size_t i = 0; i < g.size(); ++i) {
     gpe_handle* h = g[i].c->h;
     const size_t stride = pstride ? h->pstride : (size_t)h->nblk;
     for (int q = 0; q < nq; ++q)
       if (nb[i].nb[q] < 0 || (size_t)nb[i].nb[q] > stride) return fail(h0, GPE_EINVAL, "finalize: slot count");
-    recs[i] = FinArgs{h->part, h->res, gram[i], h->ticket, stride, nb[i], cg ? h->res + CG_DONE : nullptr};
+    (*recs)[i] = FinArgs{h->part, h->res, gram[i], h->ticket, stride, nb[i], cg ? h->res + CG_DONE : nullptr};
   }
+  return GPE_OK;
+}
+
+gpe_status fin(gpe_batch* b, const std::vector<Item>& g, int nq, int post, const std::vector<double*>& gram,
+               const std::vector<SlotCounts>& nb, bool pstride, bool cg = false) {
+  gpe_handle* h0 = b->hs[0];
+  std::vector<FinArgs> recs;
+  GPE_TRY(fin_records(b, g, nq, gram, nb, pstride, cg, &recs));
   const void* d = nullptr;
   GPE_TRY(b->sg.put(h0, b->st, recs.data(), sizeof(FinArgs) * recs.size(), &d));
   GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(d), (int)recs.size(), nq, post, b->F, b->st));
   return GPE_OK;
+}
+
+// Workgroup offsets of a batched launch (nblk[i] workgroups for problem i).
+gpe_status offsets(gpe_handle* h0, const std::vector<int>& nblk, std::vector<int>* blk0) {
+  blk0->assign(nblk.size() + 1, 0);
+  for (size_t i = 0; i < nblk.size(); ++i) {
+    if (nblk[i] < 1) return fail(h0, GPE_EINVAL, "batched launch: empty problem");
+    (*blk0)[i + 1] = (*blk0)[i] + nblk[i];
+  }
+  return GPE_OK;
+}
+
+template <typename A> Stager::Seg seg(const std::vector<A>& v, const void** d) {
+  return Stager::Seg{v.data(), sizeof(A) * v.size(), d};
 }
 
 SlotCounts all_slots(int v) {
@@ -324,12 +347,14 @@ gpe_status ex_lap(gpe_batch* b, std::vector<Item>& g) {
 }
 
 // Batched HVP: fused x pass, projection coefficients, remaining axis passes
-// with the projection in the last one, kappa (same stages as hvp_enq).
+// with the projection in the last one, kappa (same stages as hvp_enq).  Every
+// launch's records are built first and staged with one copy.
 template <typename T>
 gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
+  gpe_handle* h0 = b->hs[0];
   const size_t m = g.size();
   std::vector<XpassArgs<T>> xr(m);
-  std::vector<int> xb(m);
+  std::vector<int> xb(m), x0;
   std::vector<SlotCounts> nb(m, all_slots(0));
   for (size_t i = 0; i < m; ++i) {
     gpe_handle* h = g[i].c->h;
@@ -343,47 +368,83 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
     xb[i] = xpass_batch_blocks(h->ax[0].n, h->F, b->xvar, h->npts);
     for (int q = 0; q < 7; ++q) nb[i].nb[q] = xb[i];
   }
-  GPE_TRY(launch_records(b, xr, xb, [&](const XpassArgs<T>* d, const Span& sp) {
-    return xpass_batched<T>(b->F, b->xvar, d, sp, b->st);
-  }));
+  GPE_TRY(offsets(h0, xb, &x0));
   std::vector<double*> gram(m);
   for (size_t i = 0; i < m; ++i) gram[i] = g[i].c->h->gram_pt;
-  if (riem) GPE_TRY(fin(b, g, 7, POST_HVP_AB, gram, nb, true, cg));
+  std::vector<FinArgs> fab;
+  if (riem) GPE_TRY(fin_records(b, g, 7, gram, nb, true, cg, &fab));
+  // remaining stages: the 1-D projection, or the other axis passes
+  std::vector<ProjArgs<T, T, false>> pr;
+  std::vector<int> pb, p0;
+  std::vector<std::vector<LapArgs<T>>> lr(b->dim);
+  std::vector<std::vector<int>> l0(b->dim);
   int nq = 7;
   if (b->dim == 1) {
     if (riem) {
-      std::vector<ProjArgs<T, T, false>> pr(m);
-      std::vector<int> pb(m);
+      pr.resize(m);
+      pb.resize(m);
       for (size_t i = 0; i < m; ++i) {
         const gpe_handle* h = g[i].c->h;
         pr[i] = ProjArgs<T, T, false>{sizeof(T) == 8 ? h->Xp : h->Xp32, g[i].r->c, g[i].r->c, h->res + 32, 0.0, 0.0,
                                       nullptr, h->npts, h->F};
         pb[i] = h->nblk;
       }
-      GPE_TRY(ops(b, pr, pb));
+      GPE_TRY(offsets(h0, pb, &p0));
     }
   } else {
     for (int a = 1; a < b->dim; ++a) {
       const bool proj = riem && a == b->dim - 1;
-      std::vector<LapArgs<T>> lr(m);
+      lr[a].resize(m);
       std::vector<int> lb(m);
       for (size_t i = 0; i < m; ++i) {
         const gpe_handle* h = g[i].c->h;
         const LapAxis& ax = h->ax[a];
         const Req& r = *g[i].r;
-        lr[i] = LapArgs<T>{r.a, r.c, r.c, twid<T>(ax), proj ? (sizeof(T) == 8 ? h->Xp : h->Xp32) : nullptr,
-                           h->res + 32, h->part, ax.lamc, ax.nlines, h->npts, h->pstride, ax.inner, ax.n,
-                           cg ? h->res + CG_DONE : nullptr};
+        lr[a][i] = LapArgs<T>{r.a, r.c, r.c, twid<T>(ax), proj ? (sizeof(T) == 8 ? h->Xp : h->Xp32) : nullptr,
+                              h->res + 32, h->part, ax.lamc, ax.nlines, h->npts, h->pstride, ax.inner, ax.n,
+                              cg ? h->res + CG_DONE : nullptr};
         lb[i] = lap_batch_blocks(ax.n, ax.nlines);
         nb[i].nb[6 + a] = lb[i];
       }
-      GPE_TRY(launch_records(b, lr, lb, [&](const LapArgs<T>* d, const Span& sp) {
-        return lap_batched<T>(d, sp, b->F, 6 + a, b->st);
-      }));
+      GPE_TRY(offsets(h0, lb, &l0[a]));
       nq = 7 + a;
     }
   }
-  return fin(b, g, nq, cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E, gram, nb, true, cg);
+  std::vector<FinArgs> fk;
+  GPE_TRY(fin_records(b, g, nq, gram, nb, true, cg, &fk));
+
+  // one staging copy for every launch below
+  const void *dx = nullptr, *dx0 = nullptr, *dab = nullptr, *dp = nullptr, *dp0 = nullptr, *dk = nullptr;
+  const void* dl[3] = {nullptr, nullptr, nullptr};
+  const void* dl0[3] = {nullptr, nullptr, nullptr};
+  std::vector<Stager::Seg> segs = {seg(xr, &dx), seg(x0, &dx0)};
+  if (riem) segs.push_back(seg(fab, &dab));
+  if (!pr.empty()) {
+    segs.push_back(seg(pr, &dp));
+    segs.push_back(seg(p0, &dp0));
+  }
+  for (int a = 1; a < b->dim; ++a) {
+    segs.push_back(seg(lr[a], &dl[a]));
+    segs.push_back(seg(l0[a], &dl0[a]));
+  }
+  segs.push_back(seg(fk, &dk));
+  GPE_TRY(b->sg.put_all(h0, b->st, segs.data(), segs.size()));
+
+  const int n = (int)m;
+  GPE_HIP(h0, xpass_batched<T>(b->F, b->xvar, reinterpret_cast<const XpassArgs<T>*>(dx),
+                               Span{reinterpret_cast<const int*>(dx0), n, x0.back()}, b->st));
+  if (riem)
+    GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(dab), n, 7, POST_HVP_AB, b->F, b->st));
+  using PA = ProjArgs<T, T, false>;
+  if (!pr.empty())
+    GPE_HIP(h0, launch_batched<PA>(reinterpret_cast<const PA*>(dp), Span{reinterpret_cast<const int*>(dp0), n, p0.back()},
+                                   b->st));
+  for (int a = 1; a < b->dim; ++a)
+    GPE_HIP(h0, lap_batched<T>(reinterpret_cast<const LapArgs<T>*>(dl[a]),
+                               Span{reinterpret_cast<const int*>(dl0[a]), n, l0[a].back()}, b->F, 6 + a, b->st));
+  const int post = cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E;
+  GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(dk), n, nq, post, b->F, b->st));
+  return GPE_OK;
 }
 
 gpe_status ex_hvp(gpe_batch* b, std::vector<Item>& g) {
@@ -401,20 +462,33 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
     for (auto& it : g) GPE_TRY(cg_step_enq(it.c->h, it.r->a, it.r->b, it.r->c, it.r->d));
     return GPE_OK;
   }
+  // the update and its finalize staged with one copy
+  gpe_handle* h0 = b->hs[0];
+  std::vector<SlotCounts> sc(g.size());
+  for (size_t i = 0; i < g.size(); ++i) sc[i] = all_slots(g[i].c->h->nblk);
+  std::vector<FinArgs> fr;
+  GPE_TRY(fin_records(b, g, 1, no_gram(g.size()), sc, false, true, &fr));
   auto run = [&](auto tag) -> gpe_status {
     using A = decltype(tag);
     std::vector<A> recs(g.size());
-    std::vector<int> nb(g.size());
+    std::vector<int> nb(g.size()), b0;
     for (size_t i = 0; i < g.size(); ++i) {
       const gpe_handle* h = g[i].c->h;
       const Req& r = *g[i].r;
       recs[i] = A{r.a, r.b, r.c, r.d, h->part, 0.0, h->nel, h->res + CG_ALPHA, h->res + CG_DONE};
       nb[i] = h->nblk;
     }
-    return ops(b, recs, nb);
+    GPE_TRY(offsets(h0, nb, &b0));
+    const void *dr = nullptr, *d0 = nullptr, *df = nullptr;
+    const Stager::Seg segs[3] = {seg(recs, &dr), seg(b0, &d0), seg(fr, &df)};
+    GPE_TRY(b->sg.put_all(h0, b->st, segs, 3));
+    const int n = (int)g.size();
+    GPE_HIP(h0, launch_batched<A>(reinterpret_cast<const A*>(dr), Span{reinterpret_cast<const int*>(d0), n, b0.back()},
+                                  b->st));
+    GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(df), n, 1, POST_CG_STEP, b->F, b->st));
+    return GPE_OK;
   };
-  GPE_TRY(g[0].r->a32 ? run(CgArgs<float>{}) : run(CgArgs<double>{}));
-  return fin_nblk(b, g, 1, POST_CG_STEP, no_gram(g.size()), true);
+  return g[0].r->a32 ? run(CgArgs<float>{}) : run(CgArgs<double>{});
 }
 
 gpe_status ex_cginit(gpe_batch* b, std::vector<Item>& g) {
@@ -478,19 +552,27 @@ gpe_status Stager::put(gpe_handle* h, hipStream_t st, const void* src, size_t by
 
 gpe_status Stager::put2(gpe_handle* h, hipStream_t st, const void* a, size_t na, const void* b, size_t nb,
                         const void** da, const void** db) {
-  const size_t oa = (na + 15) / 16 * 16;
-  const size_t bytes = oa + nb;
+  const Seg s[2] = {{a, na, da}, {b, nb, db}};
+  return put_all(h, st, s, 2);
+}
+
+gpe_status Stager::put_all(gpe_handle* h, hipStream_t st, const Seg* segs, size_t n) {
+  size_t bytes = 0;
+  for (size_t k = 0; k < n; ++k) bytes = (bytes + 15) / 16 * 16 + segs[k].bytes;
   const size_t need = (bytes + kAlign - 1) / kAlign * kAlign;
   if (need > cap) return fail(h, GPE_ENOMEM, "batched launch records exceed the staging arena");
   if (off + need > cap) {
     GPE_HIP(h, hipStreamSynchronize(st));   // every staged record has been consumed
     off = 0;
   }
-  std::memcpy(host + off, a, na);
-  std::memcpy(host + off + oa, b, nb);
+  size_t o = 0;
+  for (size_t k = 0; k < n; ++k) {
+    o = (o + 15) / 16 * 16;
+    std::memcpy(host + off + o, segs[k].src, segs[k].bytes);
+    *segs[k].dptr = dev + off + o;
+    o += segs[k].bytes;
+  }
   GPE_HIP(h, hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st));
-  *da = dev + off;
-  *db = dev + off + oa;
   off += need;
   return GPE_OK;
 }

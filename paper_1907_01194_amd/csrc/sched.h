@@ -112,6 +112,13 @@ struct Stager {
   // first's size rounded up to 16 bytes.
   gpe_status put2(gpe_handle* h, hipStream_t st, const void* a, size_t na, const void* b, size_t nb,
                   const void** da, const void** db);
+  // Any number of arrays staged back to back (16-byte aligned) with one copy.
+  struct Seg {
+    const void* src;
+    size_t bytes;
+    const void** dptr;
+  };
+  gpe_status put_all(gpe_handle* h, hipStream_t st, const Seg* segs, size_t n);
 };
 
 // Run queued operations and the rounds of lock-step drivers.
