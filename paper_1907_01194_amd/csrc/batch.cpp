@@ -299,15 +299,7 @@ gpe_status elementwise(gpe_batch* b, std::vector<Item>& g, A (*rec)(const Req&),
 }
 
 template <typename TO> DiffArgs<double, double, TO> diff_rec(const Req& r) { return {r.a, r.b, r.c, r.n}; }
-// the CG direction update takes beta from the problem's CG state and stops with it
-template <typename T> AxpbyArgs<T> axpby_rec(const Req& r) {
-  AxpbyArgs<T> a{r.a, r.c, r.s0, r.s1, r.n};
-  if (r.cg) {
-    a.bdev = r.dres + CG_BETA;
-    a.skip = r.dres + CG_DONE;
-  }
-  return a;
-}
+template <typename T> AxpbyArgs<T> axpby_rec(const Req& r) { return {r.a, r.c, r.s0, r.s1, r.n}; }
 template <typename TI, typename TO> ConvArgs<TI, TO> copy_rec(const Req& r) { return {r.a, r.c, r.n}; }
 
 gpe_status ex_diff(gpe_batch* b, std::vector<Item>& g) {
@@ -491,6 +483,25 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
   return g[0].r->a32 ? run(CgArgs<float>{}) : run(CgArgs<double>{});
 }
 
+gpe_status ex_cgdir(gpe_batch* b, std::vector<Item>& g) {
+  if (!b || g.size() == 1) {
+    for (auto& it : g) GPE_TRY(cg_dir_enq(it.c->h, it.r->a, it.r->c, it.r->d, (int)it.r->s0));
+    return GPE_OK;
+  }
+  auto run = [&](auto tag) -> gpe_status {
+    using A = decltype(tag);
+    std::vector<A> recs(g.size());
+    std::vector<int> nb(g.size());
+    for (size_t i = 0; i < g.size(); ++i) {
+      const Req& r = *g[i].r;
+      recs[i] = A{r.a, r.c, r.d, g[i].c->h->res, (int)r.s0, r.n};
+      nb[i] = elementwise_blocks(r.n);
+    }
+    return ops(b, recs, nb);
+  };
+  return g[0].r->a32 ? run(CgDirArgs<float>{}) : run(CgDirArgs<double>{});
+}
+
 gpe_status ex_cginit(gpe_batch* b, std::vector<Item>& g) {
   if (!b || g.size() == 1) {
     for (auto& it : g) GPE_TRY(cg_init_enq(it.c->h, it.r->s0, it.r->s1, (int)it.r->n));
@@ -516,6 +527,7 @@ gpe_status execute(gpe_batch* b, int kind, std::vector<Item>& g) {
     case RQ_HVP: return ex_hvp(b, g);
     case RQ_CG: return ex_cg(b, g);
     case RQ_CGINIT: return ex_cginit(b, g);
+    case RQ_CGDIR: return ex_cgdir(b, g);
     default: return fail(g[0].c->h, GPE_EINVAL, "unknown queued operation");
   }
 }

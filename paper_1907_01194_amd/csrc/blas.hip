@@ -250,12 +250,10 @@ hipError_t scale_comps(int K, const void* u, const void* xi, double t, const dou
 // ----------------------------------------------------------------- vector updates
 template <typename T>
 __device__ void run_op(const AxpbyArgs<T>& a, int blk, int nblk) {
-  if (a.skip && *a.skip != 0.0) return;
   auto x = reinterpret_cast<const c_t<T>*>(a.x);
   auto y = reinterpret_cast<c_t<T>*>(a.y);
-  const double bv = a.bdev ? *a.bdev : a.b;
-  const T ca = (T)a.a, cb = (T)bv;
-  const bool keep = bv != 0.0;
+  const T ca = (T)a.a, cb = (T)a.b;
+  const bool keep = a.b != 0.0;
   for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
     const c_t<T> xv = x[e];
     c_t<T> yv;
@@ -287,17 +285,57 @@ __device__ void run_op(const CgArgs<T>& a, int blk, int nblk) {
   // last element first: the HVP before this update ends on the last component
   for (size_t f = (size_t)blk * blockDim.x + threadIdx.x; f < a.n; f += (size_t)nblk * blockDim.x) {
     const size_t e = a.n - 1 - f;
-    const c_t<T> pv = p[e], qv = q[e];
-    c_t<T> zv = z[e], rv = r[e];
-    zv.x += ca * pv.x;
-    zv.y += ca * pv.y;
+    const c_t<T> qv = q[e];
+    c_t<T> rv = r[e];
+    if (z) {
+      const c_t<T> pv = p[e];
+      c_t<T> zv = z[e];
+      zv.x += ca * pv.x;
+      zv.y += ca * pv.y;
+      z[e] = zv;
+    }
     rv.x += ca * qv.x;
     rv.y += ca * qv.y;
-    z[e] = zv;
     r[e] = rv;
     acc[0] += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
   }
   block_partials_any<1>(acc, a.part, nblk, blk);
+}
+
+template <typename T>
+__device__ void run_op(const CgDirArgs<T>& a, int blk, int nblk) {
+  const double* c = a.res;
+  if (c[CG_IT] != (double)(a.iter + 1)) return;   // the iteration stopped before its update, or never ran
+  const bool zupd = c[CG_REASON] != (double)CG_STOP_CURVATURE;
+  const bool pupd = c[CG_DONE] == 0.0;
+  if (!zupd && !pupd) return;
+  auto r = reinterpret_cast<const c_t<T>*>(a.r);
+  auto p = reinterpret_cast<c_t<T>*>(a.p);
+  auto z = reinterpret_cast<c_t<T>*>(a.z);
+  const T ca = (T)c[CG_ALPHA];
+  const double bv = c[CG_BETA];
+  const T cm = T(-1), cb = (T)bv;
+  const bool keep = bv != 0.0;
+  for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
+    const c_t<T> pv = p[e];
+    if (zupd) {
+      c_t<T> zv = z[e];
+      zv.x += ca * pv.x;
+      zv.y += ca * pv.y;
+      z[e] = zv;
+    }
+    if (pupd) {
+      const c_t<T> rv = r[e];
+      c_t<T> v;
+      v.x = cm * rv.x;
+      v.y = cm * rv.y;
+      if (keep) {
+        v.x += cb * pv.x;
+        v.y += cb * pv.y;
+      }
+      p[e] = v;
+    }
+  }
 }
 
 template <typename T>
@@ -403,6 +441,8 @@ GPE_OP(AxpbyArgs<double>)
 GPE_OP(AxpbyArgs<float>)
 GPE_OP(CgArgs<double>)
 GPE_OP(CgArgs<float>)
+GPE_OP(CgDirArgs<double>)
+GPE_OP(CgDirArgs<float>)
 GPE_OP(DotArgs<double, double>)
 GPE_OP(DotArgs<float, float>)
 GPE_OP(DotArgs<double, float>)

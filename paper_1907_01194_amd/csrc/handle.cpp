@@ -454,21 +454,19 @@ static gpe_status cg_step_t(gpe_handle* h, const void* p, const void* q, void* z
 }
 
 template <typename T>
-static gpe_status cg_dir_t(gpe_handle* h, const void* r, void* p) {
-  AxpbyArgs<T> a{r, p, -1.0, 0.0, h->nel};
-  a.bdev = h->res + CG_BETA;
-  a.skip = h->res + CG_DONE;
-  GPE_KT(h, KK_VECTOR, launch_single(a, elementwise_blocks(h->nel), h->st));
+static gpe_status cg_dir_t(gpe_handle* h, const void* r, void* p, void* z, int iter) {
+  GPE_KT(h, KK_VECTOR, launch_single(CgDirArgs<T>{r, p, z, h->res, iter, h->nel}, elementwise_blocks(h->nel), h->st));
   return GPE_OK;
+}
+
+gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p, void* z, int iter) {
+  return work32(h) ? cg_dir_t<float>(h, r, p, z, iter) : cg_dir_t<double>(h, r, p, z, iter);
 }
 
 gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r) {
   return work32(h) ? cg_step_t<float>(h, p, q, z, r) : cg_step_t<double>(h, p, q, z, r);
 }
 
-gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p) {
-  return work32(h) ? cg_dir_t<float>(h, r, p) : cg_dir_t<double>(h, r, p);
-}
 
 gpe_status cg_state_read(gpe_handle* h, CgState* cs) {
   const double* c = h->hres;

@@ -176,10 +176,8 @@ template <typename T> struct AxpbyArgs {   // y = a x + b y; b == 0: y = a x (y 
   void* y;
   double a, b;
   size_t n;
-  const double* bdev = nullptr;   // b from device memory when set
-  const double* skip = nullptr;
 };
-template <typename T> struct CgArgs {      // z += a p; r += a q; partials of ||r||^2
+template <typename T> struct CgArgs {      // z += a p (z null: skipped, p not read); r += a q; partials of ||r||^2
   const void* p;
   const void* q;
   void* z;
@@ -189,6 +187,18 @@ template <typename T> struct CgArgs {      // z += a p; r += a q; partials of ||
   size_t n;
   const double* adev = nullptr;   // a from device memory when set
   const double* skip = nullptr;
+};
+// Closing step of iteration iter of a device-resident CG (state in res[CG_*]):
+// if that iteration reached its update (res[CG_IT] == iter + 1), z += alpha p
+// unless it stopped on curvature, then p = -r + beta p unless the CG has
+// stopped.  Reads p before overwriting it; r is not read once stopped.
+template <typename T> struct CgDirArgs {
+  const void* r;
+  void* p;
+  void* z;
+  const double* res;
+  int iter;
+  size_t n;
 };
 // Start of a device-resident CG: rr = res[0] (the preceding reduction), not
 // stopped, no iteration yet, with the given tolerance, curvature factor and cap.

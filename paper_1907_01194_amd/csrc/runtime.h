@@ -177,9 +177,10 @@ gpe_status dot_host(gpe_handle* h, const void* a, bool a32, const void* b, bool 
 
 // Device-resident truncated CG (state in h->res[CG_*], see kernels.h), work
 // precision: cg_init_enq after a reduction of ||r||^2 into res[0]; per
-// iteration hvp_enq(..., cg = true), cg_step_enq (z += alpha p, r += alpha q,
-// residual and cap tests) and cg_dir_enq (p = -r + beta p).  After a fetch
-// cg_state_read reports where the CG stands.
+// iteration i (from 0) hvp_enq(..., cg = true), cg_step_enq (r += alpha q,
+// residual and cap tests; z null) and cg_dir_enq (z += alpha p, then
+// p = -r + beta p, see CgDirArgs).  After a fetch cg_state_read reports where
+// the CG stands.
 struct CgState {
   bool done;
   int reason;    // CG_STOP_*
@@ -188,7 +189,7 @@ struct CgState {
 };
 gpe_status cg_init_enq(gpe_handle* h, double tol, double eps, int maxit);
 gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r);
-gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p);
+gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p, void* z, int iter);
 gpe_status cg_state_read(gpe_handle* h, CgState* cs);
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);

@@ -27,14 +27,14 @@ enum ReqKind {
   RQ_SCALE,      // c (c128) = sig_i (a_i + s0 b_i), a c128, b in b32 or null
   RQ_DOT,        // <a, b> over n elements (a32, b32); read with dot_read
   RQ_DIFF,       // c (c32) = a - b (both c128), n elements
-  RQ_AXPBY,      // c = s0 a + s1 c over n elements, precision a32 (s1 == 0: c not read);
-                 // cg: s1 is the device-resident CG's beta (in dres), skipped once it stopped
+  RQ_AXPBY,      // c = s0 a + s1 c over n elements, precision a32 (s1 == 0: c not read)
   RQ_COPY,       // c (c32) = a (a32), or 0 if a is null, n elements
   RQ_LAP,        // c = L a, precision a32 (every axis)
   RQ_HVP,        // c = Hess a (work precision) at the set point, flag: Riemannian, s0 = sigma;
                  // read with hvp_read; cg: an iteration of the device-resident CG
-  RQ_CG,         // device-resident CG update: z = c += alpha a, r = d += alpha b, tests
+  RQ_CG,         // device-resident CG update: r = d += alpha b, tests (z = c += alpha a if c)
   RQ_CGINIT,     // start the device-resident CG: tolerance s0, curvature factor s1, cap n
+  RQ_CGDIR,      // close CG iteration (int)s0: z = d += alpha c, c = -a + beta c (see CgDirArgs)
   RQ_COUNT
 };
 
@@ -48,7 +48,6 @@ struct Req {
   double sig[7] = {0, 0, 0, 0, 0, 0, 0};
   double* gram = nullptr;
   size_t n = 0;
-  double* dres = nullptr;   // the problem's res array (device) for cg requests
   bool a32 = false, b32 = false, c32 = false, flag = false, cg = false;
 };
 

@@ -187,9 +187,10 @@ Req rq_hvp(const void* Z, void* HZ, bool riem, double sigma, bool w32) {
   r.a32 = r.c32 = w32;
   return r;
 }
-// One iteration of the device-resident truncated CG: A p, the update of z and
-// r with the tests, the new direction p = -r + beta p.
-void push_cg_iteration(Ctx& c, void* p, void* Ap, void* z, void* r, double sigma, bool w32) {
+// One iteration (number iter from 0) of the device-resident truncated CG:
+// A p, the update of r with the tests, then z += alpha p and the new direction
+// p = -r + beta p in one pass over p.
+void push_cg_iteration(Ctx& c, void* p, void* Ap, void* z, void* r, double sigma, bool w32, int iter) {
   Req h;
   h.kind = RQ_HVP;
   h.a = p;
@@ -201,16 +202,20 @@ void push_cg_iteration(Ctx& c, void* p, void* Ap, void* z, void* r, double sigma
   c.push(h);
   Req u;
   u.kind = RQ_CG;
-  u.a = p;
   u.b = Ap;
-  u.c = z;
   u.d = r;
   u.a32 = u.c32 = w32;
   u.cg = true;
   c.push(u);
-  Req d = rq_axpby(-1.0, r, 0.0, p, w32, c.h->nel);
+  Req d;
+  d.kind = RQ_CGDIR;
+  d.a = r;
+  d.c = p;
+  d.d = z;
+  d.s0 = iter;
+  d.n = c.h->nel;
+  d.a32 = d.c32 = w32;
   d.cg = true;
-  d.dres = c.h->res;
   c.push(d);
 }
 
@@ -401,8 +406,9 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     }
     c.push(rq_cginit(cg_tol, eps_c, cg_cap));
     CgState cs{};
+    int queued = 0;
     for (int kstep = 2;; kstep = std::min(2 * kstep, 16)) {
-      for (int j = 0; j < kstep; ++j) push_cg_iteration(c, p, Ap, cz, r, sigma, w32);
+      for (int j = 0; j < kstep; ++j) push_cg_iteration(c, p, Ap, cz, r, sigma, w32, queued++);
       ROUND;
       CO_TRY(cg_state_read(h, &cs));
       if (cs.done) break;
