@@ -363,8 +363,11 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
   GPE_TRY(offsets(h0, xb, &x0));
   std::vector<double*> gram(m);
   for (size_t i = 0; i < m; ++i) gram[i] = g[i].c->h->gram_pt;
+  // few x-pass workgroups everywhere: the last axis pass forms the projection coefficients
+  bool ab_local = riem && b->dim >= 2;
+  for (size_t i = 0; i < m; ++i) ab_local = ab_local && xb[i] <= kAbLocalMax;
   std::vector<FinArgs> fab;
-  if (riem) GPE_TRY(fin_records(b, g, 7, gram, nb, true, cg, &fab));
+  if (riem && !ab_local) GPE_TRY(fin_records(b, g, 7, gram, nb, true, cg, &fab));
   // remaining stages: the 1-D projection, or the other axis passes
   std::vector<ProjArgs<T, T, false>> pr;
   std::vector<int> pb, p0;
@@ -395,6 +398,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
         lr[a][i] = LapArgs<T>{r.a, r.c, r.c, twid<T>(ax), proj ? (sizeof(T) == 8 ? h->Xp : h->Xp32) : nullptr,
                               h->res + 32, h->part, ax.lamc, ax.nlines, h->npts, h->pstride, ax.inner, ax.n,
                               cg ? h->res + CG_DONE : nullptr};
+        if (proj && ab_local) lr[a][i].ab = AbSrc{h->part, h->pstride, xb[i], h->gram_pt, h->res};
         lb[i] = lap_batch_blocks(ax.n, ax.nlines);
         nb[i].nb[6 + a] = lb[i];
       }
@@ -410,7 +414,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
   const void* dl[3] = {nullptr, nullptr, nullptr};
   const void* dl0[3] = {nullptr, nullptr, nullptr};
   std::vector<Stager::Seg> segs = {seg(xr, &dx), seg(x0, &dx0)};
-  if (riem) segs.push_back(seg(fab, &dab));
+  if (!fab.empty()) segs.push_back(seg(fab, &dab));
   if (!pr.empty()) {
     segs.push_back(seg(pr, &dp));
     segs.push_back(seg(p0, &dp0));
@@ -425,7 +429,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
   const int n = (int)m;
   GPE_HIP(h0, xpass_batched<T>(b->F, b->xvar, reinterpret_cast<const XpassArgs<T>*>(dx),
                                Span{reinterpret_cast<const int*>(dx0), n, x0.back()}, b->st));
-  if (riem)
+  if (!fab.empty())
     GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(dab), n, 7, POST_HVP_AB, b->F, b->st));
   using PA = ProjArgs<T, T, false>;
   if (!pr.empty())

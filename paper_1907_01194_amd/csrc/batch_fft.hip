@@ -50,7 +50,7 @@ lap_batched_kernel(const LapArgs<T>* __restrict__ args, const int* __restrict__ 
     lap_body<T, NN>(reinterpret_cast<const T2*>(a.in), reinterpret_cast<const T2*>(a.acc),                    \
                     reinterpret_cast<T2*>(a.out), reinterpret_cast<const T2*>(a.tw), a.nlines, a.inner,       \
                     (T)a.lamc, F, a.npts, reinterpret_cast<const T2*>(a.X), a.coef, a.part, a.stride, slot,   \
-                    blk, a.skip);                                                                             \
+                    blk, a.skip, a.ab);                                                                       \
     break;
     GPE_BSIZES(GPE_CASE)
 #undef GPE_CASE

@@ -239,7 +239,7 @@ __device__ __forceinline__ void lap_body(const c_t<T>* __restrict__ in, const c_
                                          const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F,
                                          size_t npts, const c_t<T>* __restrict__ X, const double* __restrict__ coef,
                                          double* __restrict__ part, size_t stride, int slot, long blk,
-                                         const double* skip) {
+                                         const double* skip, const AbSrc& ab) {
   if (skip && *skip != 0.0) return;   // uniform over the workgroup
   using T2 = c_t<T>;
   constexpr int TPL = Geo<N>::TPL;
@@ -272,10 +272,54 @@ __device__ __forceinline__ void lap_body(const c_t<T>* __restrict__ in, const c_
   lc.gstride = inner;
   const T invn = T(1) / T(N);
   Epi<T> epi{acc, nullptr, T(0)};
+  double c0 = 0.0, c1 = 0.0;
+  if (X && ab.part) {   // uniform: the coefficients from the x pass's partials
+    __shared__ double red2[2][1024 / kWave];
+    __shared__ double cf[2];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = t; b < ab.n; b += blockDim.x) {
+      s0 += ab.part[b];
+      s1 += ab.part[ab.stride + b];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (t % kWave == 0) {
+      red2[0][t / kWave] = s0;
+      red2[1][t / kWave] = s1;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double w0 = 0.0, w1 = 0.0;
+      for (int w = 0; w < ((int)blockDim.x + kWave - 1) / kWave; ++w) {
+        w0 += red2[0][w];
+        w1 += red2[1][w];
+      }
+      double a11 = 0, a12 = 0, a22 = 0;
+      for (int q = 0; q < 2 * F + 1; ++q) {
+        const double l = F - q;
+        a11 += ab.gram[q];
+        a12 += l * ab.gram[q];
+        a22 += l * l * ab.gram[q];
+      }
+      const double det = a11 * a22 - a12 * a12;
+      cf[0] = (a22 * w0 - a12 * w1) / det;
+      cf[1] = (a11 * w1 - a12 * w0) / det;
+      if (blk == 0) {
+        ab.res[32] = cf[0];
+        ab.res[33] = cf[1];
+      }
+    }
+    __syncthreads();
+    c0 = cf[0];
+    c1 = cf[1];
+  } else if (X) {
+    c0 = coef[0];
+    c1 = coef[1];
+  }
   if (X && lc.valid) {
     const int comp = (int)(lc.goff / npts);          // a line never crosses a component
     epi.X = X;
-    epi.pc = (T)(coef[0] + coef[1] * (double)(F - comp));
+    epi.pc = (T)(c0 + c1 * (double)(F - comp));
   }
   double pars = 0.0;
   // Stage 0 reads global memory and uses no twiddles; the barrier that ends it

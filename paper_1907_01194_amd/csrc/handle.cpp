@@ -163,7 +163,9 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
          hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->xvar, skip, h->st));
   for (int q = 0; q < 7; ++q) nb.nb[q] = nbx;
   double* coef = h->res + 32;
-  if (riem)
+  // few x-pass workgroups: the last axis pass forms the projection coefficients itself
+  const bool ab_local = riem && h->dim >= 2 && nbx <= kAbLocalMax;
+  if (riem && !ab_local)
     GPE_KT(h, KK_FINALIZE,
            finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, skip, h->st));
   int nq = 7;
@@ -175,9 +177,11 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   } else {
     for (int a = 1; a < h->dim; ++a) {
       const bool proj = riem && a == h->dim - 1;
+      AbSrc ab;
+      if (proj && ab_local) ab = AbSrc{h->part, h->pstride, nbx, h->gram_pt, h->res};
       GPE_KT(h, KK_LAP_X + a,
              lap_axis_ex<T>(h->ax[a], Z, HZ, HZ, h->F, h->npts, proj ? Xw : nullptr, coef, h->part, h->pstride,
-                            6 + a, &nb.nb[6 + a], skip, a == 1, h->st));
+                            6 + a, &nb.nb[6 + a], skip, a == 1, ab.part ? &ab : nullptr, h->st));
       nq = 7 + a;
     }
   }

@@ -28,6 +28,22 @@ struct SlotCounts {
   int nb[32];   // kMaxQ
 };
 
+// Projection coefficients formed inside an axis pass instead of by a finalize
+// launch: every workgroup sums slots 0 and 1 of the x pass's n partials
+// (stride apart) in the same order and solves Lemma 4.1's 2x2 Gram system with
+// the set point's component norms gram; workgroup 0 also stores the two
+// coefficients in res[32..33] (part null: off).
+struct AbSrc {
+  const double* part = nullptr;
+  size_t stride = 0;
+  int n = 0;
+  const double* gram = nullptr;
+  double* res = nullptr;
+};
+// Largest x-pass workgroup count for which the last axis pass forms the
+// projection coefficients itself.
+constexpr int kAbLocalMax = 1024;
+
 // Physical constants of the pointwise terms, already combined with h:
 // zee[l] = b_l (storage order), c0 = 2 beta0 / h, ... (gradient factors)
 // and e0 = beta0 / (2h), ... (energy factors).
@@ -66,7 +82,7 @@ int xpass_variants(int n);
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nblk_out,
-                       const double* skip, int rev, hipStream_t st);
+                       const double* skip, int rev, const AbSrc* ab, hipStream_t st);
 size_t lap_max_blocks(const LapAxis& ax, int K);
 
 // Post-processing done by the single-block finalize kernel after summing the
@@ -297,6 +313,7 @@ template <typename T> struct LapArgs {
   int inner;
   int n;
   const double* skip;
+  AbSrc ab;             // projection coefficients formed in the pass (part null: from coef)
 };
 template <typename T>
 hipError_t lap_batched(const LapArgs<T>* args, const Span& sp, int F, int slot, hipStream_t st);

@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(Geo<N>::THREADS)
 lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
                 const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F, size_t npts,
                 const c_t<T>* __restrict__ X, const double* __restrict__ coef, double* __restrict__ part,
-                size_t stride, int slot, const double* skip, int rev) {
+                size_t stride, int slot, const double* skip, int rev, AbSrc ab) {
   const long blk = rev ? (long)gridDim.x - 1 - (long)blockIdx.x : (long)blockIdx.x;
-  lap_body<T, N>(in, acc, out, twg, nlines, inner, lamc, F, npts, X, coef, part, stride, slot, blk, skip);
+  lap_body<T, N>(in, acc, out, twg, nlines, inner, lamc, F, npts, X, coef, part, stride, slot, blk, skip, ab);
 }
 
 template <typename T, int N, int F, int VAR>
@@ -36,7 +36,7 @@ hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, con
 template <typename T, int N>
 static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       const double* skip, int rev, hipStream_t st) {
+                       const double* skip, int rev, const AbSrc* ab, hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int LPB = Geo<N>::LPB;
   const long nlines = ax.nlines;
@@ -46,7 +46,7 @@ static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void*
   hipLaunchKernelGGL((lap_axis_kernel<T, N>), dim3(grid), dim3(Geo<N>::THREADS), lds, st,
                      reinterpret_cast<const T2*>(in), reinterpret_cast<const T2*>(acc),
                      reinterpret_cast<T2*>(out), tw, nlines, ax.inner, (T)ax.lamc, F, npts,
-                     reinterpret_cast<const T2*>(X), coef, part, stride, slot, skip, rev);
+                     reinterpret_cast<const T2*>(X), coef, part, stride, slot, skip, rev, ab ? *ab : AbSrc{});
   if (nb) *nb = grid;
 }
 
@@ -56,7 +56,9 @@ template <typename T>
 hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* out, hipStream_t st) {
   switch (ax.n) {
 #define GPE_CASE(NN) \
-  case NN: launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, st); break;
+  case NN:                                                                                                       \
+    launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, nullptr, st); \
+    break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -67,10 +69,11 @@ hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* ou
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       const double* skip, int rev, hipStream_t st) {
+                       const double* skip, int rev, const AbSrc* ab, hipStream_t st) {
   switch (ax.n) {
-#define GPE_CASE(NN) \
-  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, skip, rev, st); break;
+#define GPE_CASE(NN)                                                                                     \
+  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, skip, rev, ab, st); \
+    break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
     default: return hipErrorInvalidValue;
@@ -161,9 +164,11 @@ bool lap_size_supported(int n) {
 template hipError_t lap_axis<double>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis<float>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis_ex<double>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
-                                        const double*, double*, size_t, int, int*, const double*, int, hipStream_t);
+                                        const double*, double*, size_t, int, int*, const double*, int,
+                                        const AbSrc*, hipStream_t);
 template hipError_t lap_axis_ex<float>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
-                                       const double*, double*, size_t, int, int*, const double*, int, hipStream_t);
+                                       const double*, double*, size_t, int, int*, const double*, int,
+                                       const AbSrc*, hipStream_t);
 template hipError_t hvp_xpass<double>(int, const LapAxis&, size_t, const void*, const void*, const void*,
                                       const double*, void*, const PwParams&, double*, size_t, int*, int,
                                       const double*, hipStream_t);
