@@ -42,10 +42,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # calibrated) and VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes),
 # by schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": "7f3b3ef1922131fc",
+    "src_hash": "bad9f4f2b2109094",
     "hvp_xpass": {
-        "traffic": {"fp64": {"0": 1109259235, "1": 1097961791, "2": 1089082058},
-                    "mixed": {"0": 482119068, "1": 481941747, "2": 479460875}},
+        "traffic": {"fp64": {"0": 1106788223, "1": 1097933451, "2": 1088466717},
+                    "mixed": {"0": 482389904, "1": 480248912, "2": 479403257}},
         "valu": {"fp64": {"0": 61161472, "1": 63971328, "2": 61128704},
                  "mixed": {"0": 64700416, "1": 63512576, "2": 60817408}},
     },
