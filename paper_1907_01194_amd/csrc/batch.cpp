@@ -455,55 +455,47 @@ gpe_status ex_hvp(gpe_batch* b, std::vector<Item>& g) {
 
 gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
   if (!b || g.size() == 1) {
-    for (auto& it : g) GPE_TRY(cg_step_enq(it.c->h, it.r->a, it.r->b, it.r->c, it.r->d));
+    for (auto& it : g) {
+      const Req& r = *it.r;
+      GPE_TRY(cg_step_enq(it.c->h, nullptr, r.b, nullptr, r.d));
+      GPE_TRY(cg_dir_enq(it.c->h, r.d, r.c, const_cast<void*>(r.a), (int)r.s0));
+    }
     return GPE_OK;
   }
-  // the update and its finalize staged with one copy
+  // the update, its finalize and the closing step staged with one copy
   gpe_handle* h0 = b->hs[0];
   std::vector<SlotCounts> sc(g.size());
   for (size_t i = 0; i < g.size(); ++i) sc[i] = all_slots(g[i].c->h->nblk);
   std::vector<FinArgs> fr;
   GPE_TRY(fin_records(b, g, 1, no_gram(g.size()), sc, false, true, &fr));
-  auto run = [&](auto tag) -> gpe_status {
+  auto run = [&](auto tag, auto dtag) -> gpe_status {
     using A = decltype(tag);
+    using D = decltype(dtag);
     std::vector<A> recs(g.size());
-    std::vector<int> nb(g.size()), b0;
+    std::vector<D> drecs(g.size());
+    std::vector<int> nb(g.size()), b0, nd(g.size()), d0;
     for (size_t i = 0; i < g.size(); ++i) {
-      const gpe_handle* h = g[i].c->h;
+      gpe_handle* h = g[i].c->h;
       const Req& r = *g[i].r;
-      recs[i] = A{r.a, r.b, r.c, r.d, h->part, 0.0, h->nel, h->res + CG_ALPHA, h->res + CG_DONE};
+      recs[i] = A{nullptr, r.b, nullptr, r.d, h->part, 0.0, h->nel, h->res + CG_ALPHA, h->res + CG_DONE};
+      drecs[i] = D{r.d, r.c, const_cast<void*>(r.a), h->res, (int)r.s0, r.n};
       nb[i] = h->nblk;
+      nd[i] = elementwise_blocks(r.n);
     }
     GPE_TRY(offsets(h0, nb, &b0));
-    const void *dr = nullptr, *d0 = nullptr, *df = nullptr;
-    const Stager::Seg segs[3] = {seg(recs, &dr), seg(b0, &d0), seg(fr, &df)};
-    GPE_TRY(b->sg.put_all(h0, b->st, segs, 3));
+    GPE_TRY(offsets(h0, nd, &d0));
+    const void *dr = nullptr, *db0 = nullptr, *df = nullptr, *dd = nullptr, *dd0 = nullptr;
+    const Stager::Seg segs[5] = {seg(recs, &dr), seg(b0, &db0), seg(fr, &df), seg(drecs, &dd), seg(d0, &dd0)};
+    GPE_TRY(b->sg.put_all(h0, b->st, segs, 5));
     const int n = (int)g.size();
-    GPE_HIP(h0, launch_batched<A>(reinterpret_cast<const A*>(dr), Span{reinterpret_cast<const int*>(d0), n, b0.back()},
+    GPE_HIP(h0, launch_batched<A>(reinterpret_cast<const A*>(dr), Span{reinterpret_cast<const int*>(db0), n, b0.back()},
                                   b->st));
     GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(df), n, 1, POST_CG_STEP, b->F, b->st));
+    GPE_HIP(h0, launch_batched<D>(reinterpret_cast<const D*>(dd), Span{reinterpret_cast<const int*>(dd0), n, d0.back()},
+                                  b->st));
     return GPE_OK;
   };
-  return g[0].r->a32 ? run(CgArgs<float>{}) : run(CgArgs<double>{});
-}
-
-gpe_status ex_cgdir(gpe_batch* b, std::vector<Item>& g) {
-  if (!b || g.size() == 1) {
-    for (auto& it : g) GPE_TRY(cg_dir_enq(it.c->h, it.r->a, it.r->c, it.r->d, (int)it.r->s0));
-    return GPE_OK;
-  }
-  auto run = [&](auto tag) -> gpe_status {
-    using A = decltype(tag);
-    std::vector<A> recs(g.size());
-    std::vector<int> nb(g.size());
-    for (size_t i = 0; i < g.size(); ++i) {
-      const Req& r = *g[i].r;
-      recs[i] = A{r.a, r.c, r.d, g[i].c->h->res, (int)r.s0, r.n};
-      nb[i] = elementwise_blocks(r.n);
-    }
-    return ops(b, recs, nb);
-  };
-  return g[0].r->a32 ? run(CgDirArgs<float>{}) : run(CgDirArgs<double>{});
+  return g[0].r->a32 ? run(CgArgs<float>{}, CgDirArgs<float>{}) : run(CgArgs<double>{}, CgDirArgs<double>{});
 }
 
 gpe_status ex_cginit(gpe_batch* b, std::vector<Item>& g) {
@@ -531,7 +523,6 @@ gpe_status execute(gpe_batch* b, int kind, std::vector<Item>& g) {
     case RQ_HVP: return ex_hvp(b, g);
     case RQ_CG: return ex_cg(b, g);
     case RQ_CGINIT: return ex_cginit(b, g);
-    case RQ_CGDIR: return ex_cgdir(b, g);
     default: return fail(g[0].c->h, GPE_EINVAL, "unknown queued operation");
   }
 }

@@ -32,9 +32,9 @@ enum ReqKind {
   RQ_LAP,        // c = L a, precision a32 (every axis)
   RQ_HVP,        // c = Hess a (work precision) at the set point, flag: Riemannian, s0 = sigma;
                  // read with hvp_read; cg: an iteration of the device-resident CG
-  RQ_CG,         // device-resident CG update: r = d += alpha b, tests (z = c += alpha a if c)
+  RQ_CG,         // rest of device-resident CG iteration (int)s0: r = d += alpha b with the
+                 // tests, then z = a += alpha c and c = -d + beta c (see CgDirArgs)
   RQ_CGINIT,     // start the device-resident CG: tolerance s0, curvature factor s1, cap n
-  RQ_CGDIR,      // close CG iteration (int)s0: z = d += alpha c, c = -a + beta c (see CgDirArgs)
   RQ_COUNT
 };
 

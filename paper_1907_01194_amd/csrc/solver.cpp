@@ -202,21 +202,15 @@ void push_cg_iteration(Ctx& c, void* p, void* Ap, void* z, void* r, double sigma
   c.push(h);
   Req u;
   u.kind = RQ_CG;
+  u.a = z;
   u.b = Ap;
+  u.c = p;
   u.d = r;
+  u.s0 = iter;
+  u.n = c.h->nel;
   u.a32 = u.c32 = w32;
   u.cg = true;
   c.push(u);
-  Req d;
-  d.kind = RQ_CGDIR;
-  d.a = r;
-  d.c = p;
-  d.d = z;
-  d.s0 = iter;
-  d.n = c.h->nel;
-  d.a32 = d.c32 = w32;
-  d.cg = true;
-  c.push(d);
 }
 
 Req rq_cginit(double tol, double eps, int maxit) {
