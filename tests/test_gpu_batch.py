@@ -121,6 +121,34 @@ def test_batch_solve_mixed_uneven_grids(torch):
     b.close()
 
 
+def test_batch_solve_small_cg_cap(torch):
+    """Every truncated CG of the run stops at a cap of 4 iterations or earlier
+    (the cap stop updates z but not p, in the closing step of the iteration
+    that hit it): the batched solve still matches the same problems solved one
+    at a time with the same options, and the oracle's ground-state energy."""
+    from paper_1907_01194_amd.binding import Batch, Problem
+    from gpu_util import dev
+    specs, seeds = _pick([(8, 1), (8, 2), (8, 3)])
+    print("batch solve fp64 cg cap 4", [(s.n, s.beta[1], s.M) for s in specs], flush=True)
+    X0 = [W.initial_state(sp, sd) for sp, sd in zip(specs, seeds)]
+    opts = dict(tol=1e-6, cg_maxit=4, cg_per_digit=0.0)
+    b = Batch(specs, "fp64")
+    Xs, stats = b.newton_solve([dev(x) for x in X0], **opts)
+    for i, sp in enumerate(specs):
+        st = stats[i]
+        assert st["converged"], (i, st)
+        assert st["cg_total"] <= 4 * st["outer"]
+        assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+        ps = Problem(sp, "fp64")
+        _, s1 = ps.newton_solve(dev(X0[i]), **opts)
+        assert s1["converged"] and s1["cg_total"] <= 4 * s1["outer"]   # (counts differ: batched kernels round differently)
+        assert abs(st["E"] - s1["E"]) <= 1e-11 * abs(s1["E"])
+        ps.close()
+        _, so = oracle.solve(oracle_problem(sp), X0[i], oracle.SolveOpts(tol=1e-6))
+        assert abs(st["E"] - so.E) <= 1e-9 * abs(so.E), (i, st["E"], so.E)
+    b.close()
+
+
 def test_batch_rejects_unsupported(torch):
     from paper_1907_01194_amd.binding import Batch, GpeError
     specs = W.spin1_2d_batch(count=2, seed=1, sizes=(16,))
