@@ -462,12 +462,15 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
     }
     return GPE_OK;
   }
-  // the update, its finalize and the closing step staged with one copy
+  // the update, its finalize (none where every problem is small: the closing
+  // step applies the tests) and the closing step staged with one copy
   gpe_handle* h0 = b->hs[0];
+  bool local = true;
+  for (size_t i = 0; i < g.size(); ++i) local = local && cg_local_step(g[i].c->h);
   std::vector<SlotCounts> sc(g.size());
   for (size_t i = 0; i < g.size(); ++i) sc[i] = all_slots(g[i].c->h->nblk);
   std::vector<FinArgs> fr;
-  GPE_TRY(fin_records(b, g, 1, no_gram(g.size()), sc, false, true, &fr));
+  if (!local) GPE_TRY(fin_records(b, g, 1, no_gram(g.size()), sc, false, true, &fr));
   auto run = [&](auto tag, auto dtag) -> gpe_status {
     using A = decltype(tag);
     using D = decltype(dtag);
@@ -479,18 +482,23 @@ gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
       const Req& r = *g[i].r;
       recs[i] = A{nullptr, r.b, nullptr, r.d, h->part, 0.0, h->nel, h->res + CG_ALPHA, h->res + CG_DONE};
       drecs[i] = D{r.d, r.c, const_cast<void*>(r.a), h->res, (int)r.s0, r.n};
+      if (local) {
+        drecs[i].part = h->part;
+        drecs[i].nb = h->nblk;
+      }
       nb[i] = h->nblk;
       nd[i] = elementwise_blocks(r.n);
     }
     GPE_TRY(offsets(h0, nb, &b0));
     GPE_TRY(offsets(h0, nd, &d0));
     const void *dr = nullptr, *db0 = nullptr, *df = nullptr, *dd = nullptr, *dd0 = nullptr;
-    const Stager::Seg segs[5] = {seg(recs, &dr), seg(b0, &db0), seg(fr, &df), seg(drecs, &dd), seg(d0, &dd0)};
-    GPE_TRY(b->sg.put_all(h0, b->st, segs, 5));
+    std::vector<Stager::Seg> segs = {seg(recs, &dr), seg(b0, &db0), seg(drecs, &dd), seg(d0, &dd0)};
+    if (!local) segs.push_back(seg(fr, &df));
+    GPE_TRY(b->sg.put_all(h0, b->st, segs.data(), segs.size()));
     const int n = (int)g.size();
     GPE_HIP(h0, launch_batched<A>(reinterpret_cast<const A*>(dr), Span{reinterpret_cast<const int*>(db0), n, b0.back()},
                                   b->st));
-    GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(df), n, 1, POST_CG_STEP, b->F, b->st));
+    if (!local) GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(df), n, 1, POST_CG_STEP, b->F, b->st));
     GPE_HIP(h0, launch_batched<D>(reinterpret_cast<const D*>(dd), Span{reinterpret_cast<const int*>(dd0), n, d0.back()},
                                   b->st));
     return GPE_OK;

@@ -89,17 +89,18 @@ __device__ void finalize_body(const double* __restrict__ part, size_t stride, co
         res[CG_REASON] = CG_STOP_CURVATURE;
         res[CG_DONE] = 1.0;
       } else {
-        res[CG_ALPHA] = out[CG_RR] / kappa;
+        res[CG_ALPHA] = out[cg_rr_slot((int)out[CG_IT] - 1)] / kappa;   // (CG_IT counts this iteration already)
       }
     }
   } else if (post == POST_CG_STEP) {
     const double rr = out[0];
+    const int it = (int)out[CG_IT];   // iterations done, this one included
     if (sqrt(rr) <= out[CG_TOL]) {
       res[CG_REASON] = CG_STOP_RESIDUAL;
       res[CG_DONE] = 1.0;
     } else {
-      res[CG_BETA] = rr / out[CG_RR];
-      res[CG_RR] = rr;
+      res[CG_BETA] = rr / out[cg_rr_slot(it - 1)];
+      res[cg_rr_slot(it)] = rr;
       if (out[CG_IT] >= out[CG_MAXIT]) {
         res[CG_REASON] = CG_STOP_CAP;
         res[CG_DONE] = 1.0;
@@ -304,16 +305,50 @@ __device__ void run_op(const CgArgs<T>& a, int blk, int nblk) {
 
 template <typename T>
 __device__ void run_op(const CgDirArgs<T>& a, int blk, int nblk) {
-  const double* c = a.res;
+  double* c = a.res;
   if (c[CG_IT] != (double)(a.iter + 1)) return;   // the iteration stopped before its update, or never ran
   const bool zupd = c[CG_REASON] != (double)CG_STOP_CURVATURE;
-  const bool pupd = c[CG_DONE] == 0.0;
-  if (!zupd && !pupd) return;
+  if (!zupd) return;   // a curvature stop: neither z nor p changes
+  bool pupd;
+  double bv;
+  if (a.part) {
+    // the residual and cap tests from the update's partials (uniform: every
+    // workgroup sums them in the same order; workgroup 0 stores the outcome,
+    // in slots no workgroup of this launch reads)
+    __shared__ double red[kRedThreads / kWave];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < a.nb; b += blockDim.x) s += a.part[b];
+    s = wave_sum(s);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    double rr = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + kWave - 1) / kWave; ++w) rr += red[w];
+    const int it = a.iter + 1;
+    const bool res_stop = sqrt(rr) <= c[CG_TOL];
+    bv = res_stop ? 0.0 : rr / c[cg_rr_slot(a.iter)];
+    const bool cap_stop = !res_stop && (double)it >= c[CG_MAXIT];
+    pupd = !res_stop && !cap_stop;
+    if (blk == 0 && threadIdx.x == 0) {
+      if (res_stop) {
+        c[CG_REASON] = CG_STOP_RESIDUAL;
+        c[CG_DONE] = 1.0;
+      } else {
+        c[CG_BETA] = bv;
+        c[cg_rr_slot(it)] = rr;
+        if (cap_stop) {
+          c[CG_REASON] = CG_STOP_CAP;
+          c[CG_DONE] = 1.0;
+        }
+      }
+    }
+  } else {
+    pupd = c[CG_DONE] == 0.0;
+    bv = c[CG_BETA];
+  }
   auto r = reinterpret_cast<const c_t<T>*>(a.r);
   auto p = reinterpret_cast<c_t<T>*>(a.p);
   auto z = reinterpret_cast<c_t<T>*>(a.z);
   const T ca = (T)c[CG_ALPHA];
-  const double bv = c[CG_BETA];
   const T cm = T(-1), cb = (T)bv;
   const bool keep = bv != 0.0;
   for (size_t e = (size_t)blk * blockDim.x + threadIdx.x; e < a.n; e += (size_t)nblk * blockDim.x) {
@@ -348,6 +383,7 @@ __device__ void run_op(const CgInitArgs& a, int blk, int nblk) {
   if (blk != 0 || threadIdx.x != 0) return;
   double* c = a.res;
   c[CG_RR] = c[0];
+  c[CG_RR1] = 0.0;
   c[CG_IT] = 0.0;
   c[CG_TOL] = a.tol;
   c[CG_EPS] = a.eps;

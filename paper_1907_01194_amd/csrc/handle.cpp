@@ -444,12 +444,20 @@ gpe_status cg_init_enq(gpe_handle* h, double tol, double eps, int maxit) {
   return GPE_OK;
 }
 
+// Small fields: the CG's closing step applies the residual and cap tests from
+// the update's partials itself (every one of its workgroups sums them), and
+// the update needs no finalize launch.
+bool cg_local_step(const gpe_handle* h) {
+  return h->nblk <= 256 && (size_t)h->nblk * (size_t)elementwise_blocks(h->nel) <= (size_t)1 << 20;
+}
+
 template <typename T>
 static gpe_status cg_step_t(gpe_handle* h, const void* p, const void* q, void* z, void* r) {
   CgArgs<T> a{p, q, z, r, h->part, 0.0, h->nel};
   a.adev = h->res + CG_ALPHA;
   a.skip = h->res + CG_DONE;
   GPE_KT(h, KK_VECTOR, launch_single(a, h->nblk, h->st));
+  if (cg_local_step(h)) return GPE_OK;
   SlotCounts nb;
   for (int k = 0; k < kMaxQ; ++k) nb.nb[k] = h->nblk;
   GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, 1, h->res, POST_CG_STEP, h->F, nullptr, h->ticket,
@@ -459,7 +467,12 @@ static gpe_status cg_step_t(gpe_handle* h, const void* p, const void* q, void* z
 
 template <typename T>
 static gpe_status cg_dir_t(gpe_handle* h, const void* r, void* p, void* z, int iter) {
-  GPE_KT(h, KK_VECTOR, launch_single(CgDirArgs<T>{r, p, z, h->res, iter, h->nel}, elementwise_blocks(h->nel), h->st));
+  CgDirArgs<T> a{r, p, z, h->res, iter, h->nel};
+  if (cg_local_step(h)) {
+    a.part = h->part;
+    a.nb = h->nblk;
+  }
+  GPE_KT(h, KK_VECTOR, launch_single(a, elementwise_blocks(h->nel), h->st));
   return GPE_OK;
 }
 
@@ -481,6 +494,7 @@ gpe_status cg_state_read(gpe_handle* h, CgState* cs) {
   cs->pp = c[CG_PP];
   if (cs->done && cs->reason == CG_STOP_CURVATURE) GPE_TRY(finite(h, c + CG_KAPPA, 2, "the CG curvature"));
   GPE_TRY(finite(h, c + CG_RR, 1, "the CG residual"));
+  GPE_TRY(finite(h, c + CG_RR1, 1, "the CG residual"));
   return GPE_OK;
 }
 

@@ -114,7 +114,8 @@ enum PostOp {
 // handle's res array (doubles): the stop flag doubles as the skip flag of every
 // launch of the CG iteration, so the host can queue several iterations at once.
 enum CgSlot {
-  CG_RR = 40,     // current ||r||^2
+  CG_RR = 40,     // ||r||^2 at the start of an even iteration (CG_RR1: odd), so that
+                  // the step that stores the next one never overwrites the one being read
   CG_ALPHA,       // step of the last CG update
   CG_BETA,        // direction coefficient of the last update
   CG_DONE,        // 0 while running, 1 once stopped
@@ -124,8 +125,11 @@ enum CgSlot {
   CG_REASON,      // CG_STOP_*
   CG_TOL,         // residual tolerance
   CG_EPS,         // curvature threshold factor: stop when kappa <= eps ||p||^2
-  CG_MAXIT        // iteration cap
+  CG_MAXIT,       // iteration cap
+  CG_RR1
 };
+// ||r||^2 at the start of iteration i (0-based) of the CG
+__host__ __device__ inline int cg_rr_slot(int i) { return (i & 1) ? CG_RR1 : CG_RR; }
 enum CgStop { CG_STOP_NONE = 0, CG_STOP_CURVATURE = 1, CG_STOP_RESIDUAL = 2, CG_STOP_CAP = 3 };
 // Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
 // (deterministic), then apply `post`.  ticket: a device counter that is 0
@@ -212,9 +216,14 @@ template <typename T> struct CgDirArgs {
   const void* r;
   void* p;
   void* z;
-  const double* res;
+  double* res;
   int iter;
   size_t n;
+  // part non-null: the CG update's nb partials of ||r||^2 (no finalize launch);
+  // every workgroup sums them in the same order and applies the residual and
+  // cap tests itself, and workgroup 0 stores the outcome in res
+  const double* part = nullptr;
+  int nb = 0;
 };
 // Start of a device-resident CG: rr = res[0] (the preceding reduction), not
 // stopped, no iteration yet, with the given tolerance, curvature factor and cap.

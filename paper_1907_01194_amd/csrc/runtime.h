@@ -190,6 +190,7 @@ struct CgState {
 gpe_status cg_init_enq(gpe_handle* h, double tol, double eps, int maxit);
 gpe_status cg_step_enq(gpe_handle* h, const void* p, const void* q, void* z, void* r);
 gpe_status cg_dir_enq(gpe_handle* h, const void* r, void* p, void* z, int iter);
+bool cg_local_step(const gpe_handle* h);
 gpe_status cg_state_read(gpe_handle* h, CgState* cs);
 
 gpe_status newton_solve(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_solve_stats* st);
