@@ -5,22 +5,23 @@ Workload: spin-3, 3D, 128^3 grid on [-8,8]^3, V = (x^2 + y^2 + 4 z^2)/2,
 beta = (500, 5, -5, 2), M = 0.2 (synthetic seeded inputs; no dataset).
 
 A step is one Riemannian Hessian-vector product of the regularised Newton
-model at a fixed point u, exactly as one truncated-CG iteration issues it:
-the three spectral-Laplacian axis passes, the pointwise spin-3 Hessian terms,
-the FP64 reductions for the tangent-space projection and <Z, HZ>, the
-projection, and the host read-back of <Z, HZ>.  The headline value is HVPs/s
-in mixed precision (c64 fields, FP64 reductions); the FP64 figure, both
-rooflines, time-to-ground-state for both precisions (full newton_solve:
-retraction, RGBB, ARNT, energies and gradients) and the CPU oracle timing
-ride on the same JSON line.
-
-The batched form (64 spin-1 2D problems of uneven grids in one gpe_batch:
-one batched HVP pass against the same HVPs one by one, and with
---batch-solve the lock-step Newton solve against one-by-one solves) rides on
-the same line under "batched".
+model at a fixed point u (Sec. 3 HVP formula, Lemma 4.2): the three
+spectral-Laplacian axis passes, the pointwise spin-3 Hessian terms, the FP64
+reductions of the tangent-space projection and the projection itself.  Steps
+run back to back on one stream with nothing read back (as the device-resident
+CG issues them); the same loop with the host read-back of <Z, HZ> after every
+HVP is reported beside it.  The headline value is FP64 HVPs/s; mixed
+precision (c64 fields, FP64 reductions) rides on the same line, with the
+whole HVP's HBM roofline at its compulsory bytes for both, the dominant
+kernel's own figures, time-to-ground-state for both precisions (full
+newton_solve: retraction, RGBB, ARNT, energies and gradients) with the time
+each takes to reach 1e-5 relative energy, the configurations' other solves,
+the batched form (64 spin-1 2D problems of uneven grids in one gpe_batch: one
+batched HVP pass against the same HVPs one by one, and the lock-step Newton
+solve against one-by-one solves) and the CPU oracle's timings.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-solve] [--no-cpu]
-                    [--no-batch] [--batch-solve]
+                    [--no-batch] [--no-batch-sequential]
 """
 
 import argparse
@@ -37,27 +38,26 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # (the published 78.6 TFLOP/s FP64 / non-packed FP32 vector rate, an FMA counting as 2 flops).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Per-launch counters of the dominant HVP kernel from rocprofv3 runs recorded in
-# profiles/hvp_spin3_128_*.md: HBM bytes (FETCH_SIZE / WRITE_SIZE, copy-kernel
-# calibrated) and VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes),
-# by schedule variant; valid only while the kernel sources hash to `src_hash`.
+# Per-launch HBM bytes of the HVP's kernels from rocprofv3 counter runs recorded
+# in profiles/ (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated) and the x pass's
+# VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes), by precision and
+# schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": "bad9f4f2b2109094",
-    "hvp_xpass": {
-        "traffic": {"fp64": {"0": 1106788223, "1": 1097933451, "2": 1088466717},
-                    "mixed": {"0": 482389904, "1": 480248912, "2": 479403257}},
-        "valu": {"fp64": {"0": 61161472, "1": 63971328, "2": 61128704},
-                 "mixed": {"0": 64700416, "1": 63512576, "2": 60817408}},
-    },
+    "src_hash": None,
+    "traffic": {},      # {prec: {variant: {kernel kind: bytes per launch}}}
+    "valu": {},         # {prec: {variant: VALU instructions per x-pass launch}}
 }
 
 
 def kernel_src_hash():
+    """Hash of every device source and header of the library."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1907_01194_amd", "csrc")
-    for f in ("lap.hip", "fft.h", "spin.h", "common.h"):
-        h.update(open(os.path.join(d, f), "rb").read())
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -69,12 +69,18 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
     ap.add_argument("--no-solve", action="store_true", help="skip time-to-ground-state")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--solve-time", type=float, default=45.0,
+    ap.add_argument("--solve-time", type=float, default=120.0,
                     help="wall-clock cap per solve of the benchmark physics (s)")
-    ap.add_argument("--precisions", default="mixed,fp64")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-HVP measurement")
-    ap.add_argument("--batch-solve", action="store_true",
-                    help="also time the lock-step batched solve of the 64 problems against one-by-one solves")
+    ap.add_argument("--precisions", default="fp64,mixed", help="the first is the headline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched measurements")
+    ap.add_argument("--no-batch-solve", action="store_true", help="skip the lock-step batched solve")
+    ap.add_argument("--no-batch-sequential", action="store_true",
+                    help="skip the one-by-one solves the batched solve is compared with")
+    ap.add_argument("--oracle-solves", action="store_true",
+                    help="also time the oracle's spin-2 2D 256^2 solve (minutes on the host)")
+    ap.add_argument("--variant", type=int, default=None, help="force the x-pass schedule variant")
+    ap.add_argument("--trace-solve", action="store_true",
+                    help="only the benchmark-physics solves, printing their per-iteration traces")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--paper-tables", action="store_true",
                     help="only reproduce the ARNT rows of the Sec. 7.1 tables (every magnetization, R1/R2/R3)")
@@ -112,10 +118,21 @@ def kernel_bytes(kind, K, npts, cb, rb):
     }.get(kind)
 
 
-def time_hvps(spec, prec, w, noise, steps, warmup, log):
+def hvp_bytes(K, npts, cb, rb):
+    """Compulsory bytes of one Riemannian HVP: read X, Z and V once, write HZ once."""
+    return 3 * K * npts * cb + npts * rb
+
+
+def time_hvps(spec, prec, w, noise, steps, warmup, log, variant=None):
+    """Time `steps` back-to-back Riemannian HVPs (nothing read back) with HIP
+    events on the handle's stream (torch's current stream), then the same with
+    the host read-back of <Z, HZ> after each, then a pass with the library's
+    events around every launch for the per-kernel breakdown."""
     import torch
     from paper_1907_01194_amd.binding import Problem, R1
     gp = Problem(spec, prec)
+    if variant is not None:
+        gp.set_schedule(variant)
     X = torch.from_numpy(w).cuda()
     u = gp.retract(X, None, 0.0, R1)                       # u = psi(w), on the manifold
     xi = gp.project(u, torch.from_numpy(noise).cuda())     # tangent direction
@@ -125,106 +142,132 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log):
     Z = xi.to(gp.work_dtype).contiguous()
     HZ = gp.empty(work=True)
     for _ in range(warmup):
-        gp.hvp_dot(Z, 1e-2, out=HZ)
+        gp.hvp(Z, True, 1e-2, out=HZ)
     torch.cuda.synchronize()
-    # the handle runs on torch's current stream, so these events bracket its work
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    # (1) the timed region: `steps` HVPs, nothing else on the stream
+    # (1) the timed region: `steps` HVPs back to back, nothing else on the stream
     e0.record(stream)
     t0 = time.perf_counter()
+    for _ in range(steps):
+        gp.hvp(Z, True, 1e-2, out=HZ)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    # (2) with the read-back of kappa = <Z, HZ> after every HVP (one synchronisation each)
+    e0.record(stream)
     kappa = 0.0
     for _ in range(steps):
         _, kappa = gp.hvp_dot(Z, 1e-2, out=HZ)
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / steps
-    # (2) the same HVPs again with the library's HIP events around every launch
-    # (on the handle's stream): per-kernel durations for the breakdown and the roofline
+    ms_dot = e0.elapsed_time(e1) / steps
+    # (3) the library's HIP events around every launch: per-kernel durations
     gp.timing(True)
     for _ in range(steps):
-        gp.hvp_dot(Z, 1e-2, out=HZ)
+        gp.hvp(Z, True, 1e-2, out=HZ)
     torch.cuda.synchronize()
     kt = gp.timing_read()
     gp.timing(False)
     sched = gp.schedule()
-    log("%s: x-pass schedule variant %d (autotuned; us per variant %s)" % (prec, sched[0], sched[1]))
-    log("%s: %.1f us per HVP (events), %.1f us (wall), kappa=%.6e; per-kernel pass (events around each launch):"
-        % (prec, 1e3 * ms, 1e6 * wall / steps, kappa))
+    log("%s: x-pass schedule variant %d (%s; us per variant %s)" % (
+        prec, sched[0], "forced" if variant is not None else "autotuned", sched[1]))
+    log("%s: %.1f us per HVP back to back (events), %.1f us (wall); %.1f us with the kappa read-back, "
+        "kappa=%.6e; per-kernel pass (events around each launch):" % (prec, 1e3 * ms, 1e6 * wall / steps,
+                                                                     1e3 * ms_dot, kappa))
     for k, (c, t) in sorted(kt.items(), key=lambda x: -x[1][1]):
         log("   %-12s %6d launches  %9.1f us avg" % (k, c, 1e3 * t / c))
+    gp.close()
     del gp
     torch.cuda.empty_cache()
-    return ms, kt, sched
+    return ms, ms_dot, kt, sched
 
 
-def roofline(spec, prec, ms, kt, variant):
-    """Roofline of the dominant kernel and of the whole HVP.  The fused x pass
-    is VALU-bound when its counters are on record (its VALU lane-operation rate
-    against VALU_PEAK_TOPS is then the headline fraction; its HBM rate rides
-    along), else it is reported against HBM."""
+def roofline(spec, prec, ms, kt, variant, steps):
+    """HBM roofline of the whole Riemannian HVP at its compulsory bytes (read
+    X, Z, V; write HZ) against the measured time per HVP, and the dominant
+    kernel's own figures (algorithmic bytes per launch over its average launch
+    duration; VALU lane operations when its counters are on record)."""
     K = spec.K
     npts = int(np.prod(spec.n))
     cb, rb = (16, 8) if prec == "fp64" else (8, 4)
-    # dominant kernel = largest total time among the HVP kernels
+    hb = hvp_bytes(K, npts, cb, rb)
+    hvp_gbs = hb / (ms / 1e3) / 1e9
+    valid = npts == 128 ** 3 and K == 7 and MEASURED["src_hash"] == kernel_src_hash()
+    tr = MEASURED["traffic"].get(prec, {}).get(str(variant)) if valid else None
+    traffic = None
+    if tr:
+        # kernel launches per HVP from the per-launch timing pass
+        traffic = int(sum(tr.get(k, 0) * c / steps for k, (c, _) in kt.items()))
     cand = {k: v for k, v in kt.items() if kernel_bytes(k, K, npts, cb, rb)}
     dom = max(cand, key=lambda k: cand[k][1])
     cnt, tot = cand[dom]
     per_launch_s = tot / cnt / 1e3
     b = kernel_bytes(dom, K, npts, cb, rb)
     achieved = b / per_launch_s / 1e9
-    hvp_bytes = 3 * K * npts * cb + npts * rb             # read X, Z, V; write HZ
-    hvp_gbs = hvp_bytes / (ms / 1e3) / 1e9
-    traffic = valu = None
-    if npts == 128 ** 3 and K == 7 and kernel_src_hash() == MEASURED["src_hash"]:
-        rec = MEASURED.get(dom, {})
-        traffic = rec.get("traffic", {}).get(prec, {}).get(str(variant))
-        valu = rec.get("valu", {}).get(prec, {}).get(str(variant))
-    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
-    if valu:
+    kern = {"name": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr.get(dom) if tr else None,
+            "bytes_per_launch": b, "us_per_launch": round(per_launch_s * 1e6, 2), "schedule_variant": variant}
+    valu = MEASURED["valu"].get(prec, {}).get(str(variant)) if valid else None
+    if valu and dom == "hvp_xpass":
         ops = valu * 64
         tops = ops / per_launch_s / 1e12
-        kern = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s (VALU lane operations)", "frac": round(tops / VALU_PEAK_TOPS, 4),
-                "traffic": traffic, "valu_lane_ops_per_launch": ops, "hbm": hbm}
-    else:
-        kern = dict(hbm)
-    kern.update({"name": dom, "schedule_variant": variant, "bytes_per_launch": b,
-                 "us_per_launch": round(per_launch_s * 1e6, 2)})
-    return {
-        "kernel": kern,
-        "hvp": {"bound": "hbm", "achieved": round(hvp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hvp_gbs / HBM_PEAK_GBS, 4), "compulsory_bytes": hvp_bytes,
-                "us_per_hvp": round(ms * 1e3, 2)},
-    }
+        kern["valu"] = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                        "unit": "TOP/s (VALU lane operations, non-packed)", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                        "lane_ops_per_launch": ops}
+    return {"bound": "hbm", "achieved": round(hvp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hvp_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "name": "riemannian_hvp (all its kernels, back to back)", "compulsory_bytes": hb,
+            "us_per_hvp": round(ms * 1e3, 2), "dominant_kernel": kern}
 
 
-def time_solve(spec, prec, w, limit, log):
+def time_solve(spec, prec, w, limit, log, tol=1e-6, trace=0):
     """Time-to-ground-state: newton_solve from w (device-resident before the
-    clock starts) to ||grad|| <= 1e-6, or until `limit` seconds."""
+    clock starts) to ||grad|| <= tol, or until `limit` seconds."""
     import torch
     from paper_1907_01194_amd.binding import Problem
     gp = Problem(spec, prec)
     X = torch.from_numpy(w).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    X, st = gp.newton_solve(X, check=False, tol=1e-6, time_limit=limit)
+    X, st = gp.newton_solve(X, check=False, tol=tol, time_limit=limit, trace=trace)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log("solve %s %s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
         spec.name, prec, st["E"], st["gnorm"], st["converged"], st["rgbb_iters"], st["outer"], st["cg_total"],
         st["hvp_calls"], wall))
+    gp.close()
     del gp
     torch.cuda.empty_cache()
-    return {"seconds": round(wall, 3), "E": st["E"], "gnorm": st["gnorm"], "converged": bool(st["converged"]),
-            "rgbb_iters": st["rgbb_iters"], "outer": st["outer"], "cg_total": st["cg_total"],
-            "hvp_calls": st["hvp_calls"], "t_rgbb": round(st["t_rgbb"], 3), "t_arnt": round(st["t_arnt"], 3)}
+    out = {"seconds": round(wall, 3), "E": st["E"], "gnorm": st["gnorm"], "converged": bool(st["converged"]),
+           "rgbb_iters": st["rgbb_iters"], "outer": st["outer"], "cg_total": st["cg_total"],
+           "hvp_calls": st["hvp_calls"], "t_rgbb": round(st["t_rgbb"], 3), "t_arnt": round(st["t_arnt"], 3)}
+    if trace:
+        out["_trace"] = st["trace"]
+    return out
 
 
-def batch_measure(count, steps, solve, log):
+def time_to_accuracy(entry, precs, rel=1e-5):
+    """Seconds (and HVPs) each precision's solve needs to bring E within `rel`
+    of the best energy any of them reached (from the solves' traces)."""
+    Es = [entry[p]["E"] for p in precs if p in entry]
+    Eref = min(Es)
+    out = {"relative_energy": rel, "E_ref": Eref, "E_ref_from": "lowest final energy of the solves"}
+    for p in precs:
+        tr = entry[p].pop("_trace", None)
+        hit = None
+        if tr is not None:
+            for row in tr:
+                if abs(row[1] - Eref) <= rel * abs(Eref):
+                    hit = row
+                    break
+        out[p] = None if hit is None else {"seconds": round(float(hit[0]), 3), "hvp_calls": int(hit[3])}
+    return out
+
+
+def batch_measure(count, steps, solve, sequential, log):
     """Batched form: `count` spin-1 2D problems of uneven grids (64^2, 128^2,
     256^2) and parameters in one gpe_batch.  Times one batched Riemannian HVP
     pass over all problems (one launch per kernel stage) against the same HVPs
@@ -295,7 +338,7 @@ def batch_measure(count, steps, solve, log):
         conv = sum(int(s["converged"]) for s in st)
         log("batched solve: %.2f s, %d/%d converged, max hvp %d" % (tb, conv, count, max(s["hvp_calls"] for s in st)))
         ts, E1 = 0.0, []
-        for i, sp in enumerate(specs):
+        for i, sp in enumerate(specs if sequential else []):
             p = Problem(sp, "mixed")
             x = X0[i].clone()
             torch.cuda.synchronize()
@@ -305,13 +348,14 @@ def batch_measure(count, steps, solve, log):
             ts += time.perf_counter() - t0
             E1.append(s1["E"])
             p.close()
-        dE = max(abs(a["E"] - e) / abs(e) for a, e in zip(st, E1))
-        log("one-by-one solves: %.2f s; max relative energy difference %.2e" % (ts, dE))
-        out["solve"] = {"tol": 1e-6, "batched_s": round(tb, 3), "sequential_s": round(ts, 3),
-                        "speedup": round(ts / tb, 2), "converged": conv,
+        out["solve"] = {"tol": 1e-6, "batched_s": round(tb, 3), "converged": conv,
                         "max_hvp_calls": max(s["hvp_calls"] for s in st),
-                        "total_hvp_calls": sum(s["hvp_calls"] for s in st),
-                        "max_rel_energy_diff_vs_sequential": dE}
+                        "total_hvp_calls": sum(s["hvp_calls"] for s in st)}
+        if sequential:
+            dE = max(abs(a["E"] - e) / abs(e) for a, e in zip(st, E1))
+            log("one-by-one solves: %.2f s; max relative energy difference %.2e" % (ts, dE))
+            out["solve"].update({"sequential_s": round(ts, 3), "speedup": round(ts / tb, 2),
+                                 "max_rel_energy_diff_vs_sequential": dE})
     b.close()
     torch.cuda.empty_cache()
     return out
@@ -350,8 +394,9 @@ def paper_tables(log):
     return rows
 
 
-def cpu_baseline(spec, w, noise, log):
-    """The oracle (FP64, NumPy/scipy) per Riemannian HVP on the same workload."""
+def cpu_baseline(spec, w, noise, log, reps=5):
+    """The oracle (FP64, NumPy/scipy.fft on every host core) per Riemannian HVP
+    on the same workload: the median of `reps` timed HVPs after one warm-up."""
     here = os.path.dirname(os.path.abspath(__file__))
     sys.path.insert(0, here)
     import oracle
@@ -363,15 +408,69 @@ def cpu_baseline(spec, w, noise, log):
     xi /= np.sqrt(oracle.inner(xi, xi))
     ag, bg = oracle.proj_coeffs(prob, u, oracle.grad(prob, u))
     oracle.rhess(prob, u, xi, ag, bg, 1e-2)                   # warm-up
-    reps = 2
-    t0 = time.perf_counter()
+    ts = []
     for _ in range(reps):
+        t0 = time.perf_counter()
         oracle.rhess(prob, u, xi, ag, bg, 1e-2)
-    dt = (time.perf_counter() - t0) / reps
-    log("cpu oracle: %.2f s per HVP" % dt)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    log("cpu oracle: %.2f s per HVP (median of %d: %s)" % (dt, reps, ", ".join("%.2f" % t for t in ts)))
     return {"value": round(1.0 / dt, 4), "unit": "HVP/s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": "%d Riemannian HVPs (spin-3 128^3, FP64 NumPy/scipy.fft) after 1 warm-up, "
-                      "scipy.fft workers=%d" % (reps, os.cpu_count())}
+            "sample": "median of %d Riemannian HVPs (spin-3 128^3, FP64 NumPy/scipy.fft, workers=%d) after "
+                      "1 warm-up" % (reps, os.cpu_count()),
+            "seconds_per_hvp": round(dt, 3), "seconds_each": [round(t, 3) for t in ts]}
+
+
+def oracle_solves(log):
+    """The oracle's own time-to-ground-state on the small configurations (all
+    host cores for scipy.fft): spin-1 1D 128 to ||grad|| <= 1e-8 and spin-2 2D
+    256^2 to 1e-6, from the same seeded initial states as the GPU solves."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import oracle
+    import oracle.energy as oe
+    from paper_1907_01194_amd import workloads as W
+    oe.FFT_WORKERS = os.cpu_count()
+    out = {}
+    for key, spec, seed, tol in (("spin1-1d-128", W.spin1_1d(), 1, 1e-8), ("spin2-2d-256", W.spin2_2d(), 2, 1e-6)):
+        prob = oracle.make_problem(spec.F, spec.n, spec.lo, spec.hi, spec.V, spec.beta, spec.M, spec.p, spec.q)
+        t0 = time.perf_counter()
+        _, st = oracle.solve(prob, W.initial_state(spec, seed), oracle.SolveOpts(tol=tol))
+        dt = time.perf_counter() - t0
+        log("oracle solve %s: %.2f s E=%.12f |g|=%.2e conv=%d hvp=%d" % (key, dt, st.E, st.gnorm, st.converged,
+                                                                          st.hvp_calls))
+        out[key] = {"seconds": round(dt, 3), "E": st.E, "gnorm": st.gnorm, "converged": bool(st.converged),
+                    "hvp_calls": st.hvp_calls, "tol": tol, "cores": os.cpu_count()}
+    return out
+
+
+def oracle_solves_small(log):
+    """The oracle's spin-1 1D 128 solve (a fraction of a second)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import oracle
+    import oracle.energy as oe
+    from paper_1907_01194_amd import workloads as W
+    oe.FFT_WORKERS = os.cpu_count()
+    spec = W.spin1_1d()
+    prob = oracle.make_problem(spec.F, spec.n, spec.lo, spec.hi, spec.V, spec.beta, spec.M, spec.p, spec.q)
+    t0 = time.perf_counter()
+    _, st = oracle.solve(prob, W.initial_state(spec, 1), oracle.SolveOpts(tol=1e-8))
+    dt = time.perf_counter() - t0
+    log("oracle solve spin1-1d-128: %.2f s E=%.12f |g|=%.2e" % (dt, st.E, st.gnorm))
+    return {"spin1-1d-128": {"seconds": round(dt, 3), "E": st.E, "gnorm": st.gnorm, "converged": bool(st.converged),
+                             "hvp_calls": st.hvp_calls, "tol": 1e-8, "cores": os.cpu_count()}}
+
+
+def config_solves(log):
+    """GPU time-to-ground-state of the small configurations (FP64), from the
+    same seeded initial states as the oracle's solves."""
+    from paper_1907_01194_amd import workloads as W
+    out = {}
+    for key, spec, seed, tol in (("spin1-1d-128", W.spin1_1d(), 1, 1e-8), ("spin2-2d-256", W.spin2_2d(), 2, 1e-6)):
+        out[key] = time_solve(spec, "fp64", W.initial_state(spec, seed), 120.0, log, tol=tol)
+        out[key]["tol"] = tol
+    return out
 
 
 def paper_case_solves(n, precs, log):
@@ -387,6 +486,19 @@ def paper_case_solves(n, precs, log):
     for prec in precs:
         entry[prec] = time_solve(ps, prec, pw, 300.0, log)
         entry[prec]["energy_err_vs_paper"] = abs(entry[prec]["E"] - 42.9822)
+    return entry
+
+
+def benchmark_physics_solves(spec, precs, limit, log, trace=4000):
+    """The benchmark physics (beta = (500, 5, -5, 2), gamma = (1, 1, 2)) from the
+    Sec. 7 kind of initial data, each precision to ||grad|| <= 1e-6 or the
+    time cap, with the time each takes to reach 1e-5 relative energy."""
+    from paper_1907_01194_amd import workloads as W
+    bw = W.paper_initial(spec, W.paper_U(3, None, spec.M, 3))
+    entry = {"workload": spec.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
+             "time_cap_s": limit}
+    for prec in precs:
+        entry[prec] = time_solve(spec, prec, bw, limit, log, trace=trace)
     return entry
 
 
@@ -410,32 +522,56 @@ def main():
         print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6}), flush=True)
         return
     from paper_1907_01194_amd import workloads as W
+    from paper_1907_01194_amd.binding import TRACE_NAMES
     precs = args.precisions.split(",")
     if args.solve_only:
         print(json.dumps({"time_to_ground_state": {"paper_case": paper_case_solves(args.n, precs, log)}}), flush=True)
         return
     spec = W.spin3_3d(args.n)
+    if args.trace_solve:
+        entry = benchmark_physics_solves(spec, precs, args.solve_time, log)
+        for p in precs:
+            tr = entry[p]["_trace"]
+            log("trace %s (%s):" % (p, " ".join(TRACE_NAMES)))
+            for row in tr:
+                log("  " + " ".join("%.6g" % v for v in row))
+        entry["to_1e-5_relative_energy"] = time_to_accuracy(entry, precs)
+        print(json.dumps({"benchmark_physics": entry}), flush=True)
+        return
     w = W.initial_state(spec, 3)
     noise = W.random_direction(spec, 103)
     res = {}
     for prec in precs:
-        ms, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log)
-        res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "roofline": roofline(spec, prec, ms, kt, sched[0]),
+        ms, ms_dot, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log, args.variant)
+        res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "ms_per_hvp_with_kappa_readback": ms_dot,
+                     "roofline": roofline(spec, prec, ms, kt, sched[0], args.steps),
                      "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()},
-                     "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]}}
+                     "kernel_launches_per_hvp": {k: round(c / args.steps, 2) for k, (c, t) in kt.items()},
+                     "xpass_schedule": {"variant": sched[0], "forced": args.variant is not None,
+                                        "us_per_variant": [round(x, 1) for x in sched[1]]}}
     solves = {}
     if not args.no_solve:
         solves["paper_case"] = paper_case_solves(args.n, precs, log)
-        # (b) the benchmark physics (beta = (500, 5, -5, 2), gamma = (1, 1, 2)) from the same
-        #     kind of initial data, capped: its soft modes make the Newton iteration slow
-        bw = W.paper_initial(spec, W.paper_U(3, None, spec.M, 3))
-        entry = {"workload": spec.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
-                 "time_cap_s": args.solve_time}
-        for prec in precs:
-            entry[prec] = time_solve(spec, prec, bw, args.solve_time, log)
+        entry = benchmark_physics_solves(spec, precs, args.solve_time, log)
+        entry["to_1e-5_relative_energy"] = time_to_accuracy(entry, precs)
         solves["benchmark_physics"] = entry
-    batch = None if args.no_batch else batch_measure(args.batch_count, 50, args.batch_solve, log)
-    cpu = None if args.no_cpu else cpu_baseline(spec, w, noise, log)
+        solves["configs"] = config_solves(log)
+    batch = None if args.no_batch else batch_measure(args.batch_count, 50, not args.no_batch_solve,
+                                                     not args.no_batch_sequential, log)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(spec, w, noise, log)
+        orc = {}
+        if args.oracle_solves:
+            orc = oracle_solves(log)
+        else:
+            orc = {k: v for k, v in oracle_solves_small(log).items()}
+        fp = solves.get("benchmark_physics", {}).get("fp64") if solves else None
+        if fp:
+            orc["spin3-3d-128 (estimate)"] = {
+                "kind": "estimate: oracle seconds per HVP x the GPU FP64 solve's HVP count (not run)",
+                "seconds": round(cpu["seconds_per_hvp"] * fp["hvp_calls"], 1), "hvp_calls": fp["hvp_calls"]}
+        cpu["time_to_ground_state"] = orc
     head = precs[0]
     out = {
         "metric": "HVPs/s + time-to-ground-state, spin-3 128^3, mixed vs FP64, same GPU",
@@ -448,19 +584,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64-reductions" if head == "mixed" else "f64",
+        "dtype": "f64" if head == "fp64" else "c64+f64-reductions",
         "data": "synthetic",
         "config": {"workload": spec.name, "F": spec.F, "grid": list(spec.n), "box": [spec.lo[0], spec.hi[0]],
                    "potential": "0.5*(x^2+y^2+4z^2)", "beta": list(spec.beta), "M": spec.M,
                    "precision": head},
-        "roofline": res[head]["roofline"]["kernel"],
-        "hvp_roofline": res[head]["roofline"]["hvp"],
+        "roofline": res[head]["roofline"],
         "cpu_baseline": cpu,
         "precisions": {p: {"hvp_per_s": round(r["hvp_per_s"], 2), "ms_per_hvp": round(r["ms_per_hvp"], 4),
+                           "ms_per_hvp_with_kappa_readback": round(r["ms_per_hvp_with_kappa_readback"], 4),
                            "roofline": r["roofline"], "kernels_us": r["kernels_us"],
+                           "kernel_launches_per_hvp": r["kernel_launches_per_hvp"],
                            "xpass_schedule": r["xpass_schedule"]} for p, r in res.items()},
         "time_to_ground_state": solves or None,
         "batched": batch,
+        "kernel_src_hash": kernel_src_hash(),
     }
     print(json.dumps(out), flush=True)
 

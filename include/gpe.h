@@ -59,8 +59,10 @@ typedef enum { GPE_FP64 = 0, GPE_MIXED = 1 } gpe_precision;
 typedef enum { GPE_R1_PROJECTIVE = 1, GPE_R2_ORTHOGONAL = 2, GPE_R3_CLOSED = 3 } gpe_retraction;
 
 /* Problem statement (Sec. 2 energy with mass and magnetization constraints,
- * Sec. 3 discretisation).  F in {1,2,3}; dim in {1,2,3}; n[a] even with no
- * prime factor other than 2 and 3, 4 <= n[a] <= 512 (unused axes ignored);
+ * Sec. 3 discretisation).  F in {1,2,3}; dim in {1,2,3}; each used n[a] is
+ * one of 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, i.e.
+ * 2^k or 3*2^k (Sec. 3 asks for an even n; the line transforms take radix
+ * 8/4/2 stages and at most one radix-3 stage); unused axes are ignored;
  * lo[a] < hi[a]; beta = (beta0, beta1, beta2, beta3) (beta2 used for F >= 2,
  * beta3 for F = 3); Zeeman shifts p, q give b_l = -p l + q l^2; |M| < F.
  * A negative M is handled by the symmetry M <-> -M, phi_l <-> phi_-l (Sec. 4),
@@ -112,7 +114,22 @@ typedef struct gpe_solve_opts {
    * ceil(cg_per_digit * log10(1 / min(T, ||g||^theta)))), a number of iterations
    * per decimal digit the CG residual must gain (80; 0: the fixed cap cg_maxit). */
   double cg_per_digit;
+  /* Optional trace of the run (NULL: none): host array of trace_cap rows of
+   * GPE_TRACE_COLS doubles.  One row when the RGBB warm start ends, then one
+   * per ARNT outer iteration after its acceptance test, on the finest mesh
+   * only; gpe_solve_stats.trace_len says how many rows were written (rows
+   * beyond trace_cap are dropped).  Columns: seconds since the solve began,
+   * E and ||grad|| at the current point (after the step, if accepted),
+   * cumulative Hessian-vector products, sigma of the subproblem, the ratio
+   * rho_k (NaN on the RGBB row, -Inf if no trial point was formed), truncated
+   * CG iterations, CG stop reason (0 none, 1 curvature, 2 residual, 3 cap;
+   * -1 on the RGBB row), the accepted step length t, accepted (1) or
+   * rejected (0).  Ignored by gpe_batch_newton_solve. */
+  double* trace;
+  int trace_cap;
 } gpe_solve_opts;
+
+#define GPE_TRACE_COLS 10
 
 typedef struct gpe_solve_stats {
   double E;              /* final energy (FP64) */
@@ -132,17 +149,21 @@ typedef struct gpe_solve_stats {
   int mg_levels;         /* coarse meshes actually used */
   double t_coarse;       /* seconds spent on the coarse meshes (included in t_total) */
   int polish_at;         /* outer iteration at which the FP64 polish began (-1: none) */
+  int trace_len;         /* rows written to gpe_solve_opts.trace */
 } gpe_solve_stats;
 
 /* Fill *opts with the defaults listed in gpe_solve_opts.  Never fails. */
 void gpe_solve_opts_default(gpe_solve_opts* opts);
 
-/* Create a handle for one problem.  V_host: host array of n_x*n_y*n_z doubles,
- * the potential V(x_j) on the grid (C order, x fastest), copied to the device.
+/* Create a handle for one problem.  V: n_x*n_y*n_z doubles, the potential
+ * V(x_j) on the grid (C order, x fastest), in host memory or in device memory
+ * of the current device (told apart with hipPointerGetAttributes); it is
+ * copied, so the caller keeps ownership and may free it after the call.
  * precision: gpe_precision.  stream: hipStream_t (NULL = default stream).
  * Allocates all device workspace; *out receives the handle.
- * Errors: GPE_EINVAL (bad problem, NULL pointers), GPE_ENOMEM, GPE_EHIP. */
-gpe_status gpe_create(const gpe_problem* prob, const double* V_host, int precision,
+ * Errors: GPE_EINVAL (bad problem: F, dim, an unsupported n, |M| >= F, M < 0,
+ * an empty box; NULL pointers), GPE_ENOMEM, GPE_EHIP. */
+gpe_status gpe_create(const gpe_problem* prob, const double* V, int precision,
                       void* stream, gpe_handle** out);
 
 /* Release the handle and its device memory (synchronises its stream).  NULL is a no-op. */
@@ -224,6 +245,14 @@ gpe_status gpe_newton_solve(gpe_handle* h, void* X_inout, const gpe_solve_opts* 
  * microseconds (0 where a variant was not timed). */
 gpe_status gpe_schedule(const gpe_handle* h, int* xpass_variant, float* variant_us, int nvariants);
 
+/* Force the fused x pass's schedule variant (0 .. count-1; count from
+ * gpe_schedule_count, 3 for n_x in {64, 96, 128, 256}, else 1) instead of the
+ * autotuned one, e.g. to compare every variant's results.  All variants
+ * compute the same products (they differ in rows per workgroup only).
+ * Errors: GPE_EINVAL for a variant out of range (the schedule is unchanged). */
+gpe_status gpe_set_schedule(gpe_handle* h, int xpass_variant);
+gpe_status gpe_schedule_count(const gpe_handle* h, int* nvariants);
+
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every kernel launched by the library.  gpe_timing_enable(h, 1) clears the
  * record and starts recording; gpe_timing_read synchronises and writes, for
@@ -250,8 +279,11 @@ const char* gpe_version(void);
  * that are at the same step is one launch per kernel stage (the fused HVP x
  * pass, the axis passes, the finalize, the CG updates, the energy and
  * gradient, the retraction), and the scalars of all problems come back in one
- * copy with one synchronisation.  Each problem's iteration is exactly the
- * one gpe_newton_solve makes (the same readings, tolerances and counters).
+ * copy with one synchronisation.  Each problem runs the iteration
+ * gpe_newton_solve runs (the same readings, tolerances and counters); the
+ * batched kernels may sum partial results in another order, so iteration
+ * counts and the last digits of a problem's iterates can differ from a lone
+ * solve's, while its result meets the same tolerance.
  * Every grid length of a batch must be a power of two from 16 to 512.
  */
 typedef struct gpe_batch gpe_batch;

@@ -45,7 +45,11 @@ class gpe_solve_opts(ctypes.Structure):
                 ("ls_max", c_int), ("cg_maxit", c_int), ("cg_T", c_double), ("cg_theta", c_double),
                 ("max_reject_streak", c_int), ("sigma_hat_min", c_double), ("verbose", c_int), ("time_limit", c_double),
                 ("mg_levels", c_int), ("mg_coarse_tol", c_double), ("polish_tol", c_double),
-                ("polish_window", c_int), ("cg_per_digit", c_double)]
+                ("polish_window", c_int), ("cg_per_digit", c_double),
+                ("trace", ctypes.POINTER(c_double)), ("trace_cap", c_int)]
+
+TRACE_COLS = 10
+TRACE_NAMES = ("t", "E", "gnorm", "hvp_calls", "sigma", "ratio", "cg_iters", "cg_reason", "step", "accepted")
 
 
 class gpe_solve_stats(ctypes.Structure):
@@ -53,7 +57,7 @@ class gpe_solve_stats(ctypes.Structure):
                 ("outer", c_int), ("cg_total", c_int), ("hvp_calls", c_int), ("ls_trials", c_int),
                 ("rejected", c_int), ("t_total", c_double), ("t_rgbb", c_double),
                 ("t_arnt", c_double), ("mass_err", c_double), ("mag_err", c_double),
-                ("mg_levels", c_int), ("t_coarse", c_double), ("polish_at", c_int)]
+                ("mg_levels", c_int), ("t_coarse", c_double), ("polish_at", c_int), ("trace_len", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +81,8 @@ SIGNATURES = {
     "gpe_project": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "gpe_prolong": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "gpe_schedule": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_float), c_int]),
+    "gpe_set_schedule": (c_int, [c_void_p, c_int]),
+    "gpe_schedule_count": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "gpe_timing_enable": (c_int, [c_void_p, c_int]),
     "gpe_timing_read": (c_int, [c_void_p, c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(c_int),
                                 ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
@@ -277,6 +283,15 @@ class Problem:
         self._check(lib().gpe_schedule(self.h, ctypes.byref(v), us, 3))
         return v.value, list(us)
 
+    def set_schedule(self, variant):
+        """Force x-pass schedule variant ``variant`` (see schedule_count)."""
+        self._check(lib().gpe_set_schedule(self.h, int(variant)))
+
+    def schedule_count(self):
+        n = c_int()
+        self._check(lib().gpe_schedule_count(self.h, ctypes.byref(n)))
+        return n.value
+
     def timing(self, enable=True):
         self._check(lib().gpe_timing_enable(self.h, int(bool(enable))))
 
@@ -295,13 +310,24 @@ class Problem:
         self._check(lib().gpe_constraints(self.h, self._m(X), ctypes.byref(m), ctypes.byref(g)))
         return m.value, g.value
 
-    def newton_solve(self, X, check=True, **opts):
+    def newton_solve(self, X, check=True, trace=0, **opts):
+        """Algorithm 1 from X (overwritten).  trace > 0 asks for up to `trace`
+        rows of the per-iteration trace, returned as stats["trace"] (a numpy
+        array with columns TRACE_NAMES)."""
         o = default_opts(**opts)
+        buf = None
+        if trace:
+            buf = np.zeros((int(trace), TRACE_COLS))
+            o.trace = buf.ctypes.data_as(ctypes.POINTER(c_double))
+            o.trace_cap = int(trace)
         s = gpe_solve_stats()
         st = lib().gpe_newton_solve(self.h, self._m(X), ctypes.byref(o), ctypes.byref(s))
         if st != 0 and (check or st != 5):
             self._check(st)
-        return X, s.as_dict()
+        out = s.as_dict()
+        if buf is not None:
+            out["trace"] = buf[:s.trace_len].copy()
+        return X, out
 
 
 class Batch:

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpe.so")
-SOURCES = ["lap.hip", "batch_fft.hip", "pointwise.hip", "blas.hip", "mg.hip", "handle.cpp", "solver.cpp",
+SOURCES = ["lap.hip", "batch_fft.hip", "pointwise.hip", "blas.hip", "mg.hip", "handle.cpp", "solver.cpp", "retract_scalar.cpp",
            "batch.cpp"]
 ARCH = os.environ.get("GPE_OFFLOAD_ARCH", "gfx950")
 

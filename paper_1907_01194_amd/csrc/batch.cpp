@@ -869,6 +869,8 @@ gpe_status gpe_batch_newton_solve(gpe_batch* b, void* const* X_inout, const gpe_
   if (opts) o = *opts;
   else gpe_solve_opts_default(&o);
   if (o.mg_levels > 0) return batch_fail(b, GPE_EINVAL, "a batch solves on one mesh (mg_levels must be 0)");
+  o.trace = nullptr;   // one trace buffer cannot serve many problems
+  o.trace_cap = 0;
   const size_t m = b->hs.size();
   std::vector<gpe_solve_stats> st(m);
   std::vector<Ctx> cs(m);

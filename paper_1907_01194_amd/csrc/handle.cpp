@@ -8,6 +8,7 @@
 #include <string>
 
 #include "common.h"
+#include "retract_scalar.h"
 #include "runtime.h"
 
 static std::string g_create_error;
@@ -150,8 +151,11 @@ gpe_status adopt_point(gpe_handle* h) {
 
 // cg: one iteration of the device-resident truncated CG (the launches are
 // skipped once the CG has stopped, and the last finalize runs its tests).
+// kappa: form <Z, HZ> and ||Z||^2 (res[34..35]) in a last finalize; gpe_hvp
+// without scalar outputs skips that launch.
 template <typename T>
-static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const PwParams& p, bool cg) {
+static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const PwParams& p, bool cg,
+                        bool kappa) {
   const void* Xw = sizeof(T) == 8 ? h->Xp : h->Xp32;
   const void* Yw = sizeof(T) == 8 ? h->LX64 : h->LX32;
   const T* Vw = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h->V64 : (const void*)h->V32);
@@ -185,6 +189,7 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
       nq = 7 + a;
     }
   }
+  if (!cg && !kappa) return GPE_OK;
   const int post = cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E;
   GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, post, h->F, h->gram_pt, h->ticket, skip, h->st));
   return GPE_OK;
@@ -245,12 +250,12 @@ PwParams hvp_params(const gpe_handle* h, bool riem, double sigma) {
   return p;
 }
 
-gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, bool cg) {
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, bool cg, bool kappa) {
   if (!h->has_point) return fail(h, GPE_EINVAL, "gpe_hvp before gpe_set_point");
   if (cg && !riem) return fail(h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
   const PwParams p = hvp_params(h, riem, sigma);
-  if (!work32(h)) return hvp_t<double>(h, Z, HZ, riem, p, cg);
-  return hvp_t<float>(h, Z, HZ, riem, p, cg);
+  if (!work32(h)) return hvp_t<double>(h, Z, HZ, riem, p, cg, kappa);
+  return hvp_t<float>(h, Z, HZ, riem, p, cg, kappa);
 }
 
 gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz) {
@@ -261,7 +266,7 @@ gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz) {
 }
 
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riem, double sigma, double* kappa, double* zz) {
-  GPE_TRY(hvp_enq(h, Z, HZ, riem, sigma, false));
+  GPE_TRY(hvp_enq(h, Z, HZ, riem, sigma, false, kappa || zz));
   if (!kappa && !zz) return GPE_OK;
   GPE_TRY(fetch(h));
   return hvp_read(h, kappa, zz);
@@ -292,111 +297,18 @@ gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32
   return norms_read(h, xi != nullptr, rn);
 }
 
-// Projective retraction (Sec. 6.1): sigma_l = 1/(sqrt(s)(1 - (l-M) r)) on
-// [f1, f2], r the zero of the increasing h1 on (1/(f1-M), 1/(f2-M)).
-static gpe_status sigma_projective(gpe_handle* h, const double* a, double* sig) {
-  const int K = h->K, F = h->F;
-  const double M = h->M;
-  int f1 = 1 << 20, f2 = -(1 << 20);
-  for (int i = 0; i < K; ++i)
-    if (a[i] > 0) {
-      const int l = F - i;
-      if (l < f1) f1 = l;
-      if (l > f2) f2 = l;
-    }
-  if (!(f1 < M && f2 > M)) return fail(h, GPE_EDOMAIN, "retraction argument outside Omega");
-  double lo = 1.0 / (f1 - M), hi = 1.0 / (f2 - M), t = 0.0;
-  for (int it = 0; it < 300; ++it) {
-    double f = 0.0, df = 0.0;
-    for (int i = 0; i < K; ++i) {
-      if (!(a[i] > 0)) continue;
-      const double c = (F - i) - M;
-      const double d = 1.0 - c * t;
-      f += c * a[i] / (d * d);
-      df += 2.0 * c * c * a[i] / (d * d * d);
-    }
-    if (f == 0.0) break;
-    if (f > 0) hi = t;
-    else lo = t;
-    double tn = t - f / df;
-    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-    const bool done = std::fabs(tn - t) <= 4e-16 * std::fmax(std::fabs(t), 1e-300);
-    t = tn;
-    if (done || hi - lo <= 4e-16 * std::fmax(std::fabs(lo), std::fabs(hi))) break;
-  }
-  double s = 0.0;
-  for (int i = 0; i < K; ++i) {
-    if (!(a[i] > 0)) continue;
-    const double d = 1.0 - ((F - i) - M) * t;
-    s += a[i] / (d * d);
-  }
-  const double rs = 1.0 / std::sqrt(s);
-  for (int i = 0; i < K; ++i) {
-    const int l = F - i;
-    sig[i] = (l >= f1 && l <= f2) ? rs / (1.0 - (l - M) * t) : 0.0;
-  }
-  return GPE_OK;
-}
-
-// Orthogonal retraction (Sec. 6.2): sigma_l = sqrt(r^l / sum_k a_k r^k), r the
-// positive zero of h2; searched as the sign change of sum (l-M) a_l e^{l s}.
-static gpe_status sigma_orthogonal(gpe_handle* h, const double* a, double* sig) {
-  const int K = h->K, F = h->F;
-  const double M = h->M;
-  double below = 0, above = 0;
-  for (int i = 0; i < K; ++i) {
-    if ((F - i) < M) below += a[i];
-    if ((F - i) > M) above += a[i];
-  }
-  if (!(below > 0 && above > 0)) return fail(h, GPE_EDOMAIN, "retraction argument outside Omega");
-  auto g = [&](double s) {
-    double mx = -1e300;
-    for (int i = 0; i < K; ++i) mx = std::fmax(mx, (F - i) * s);
-    double v = 0.0;
-    for (int i = 0; i < K; ++i) v += ((F - i) - M) * a[i] * std::exp((F - i) * s - mx);
-    return v;
-  };
-  double lo = -1.0, hi = 1.0;
-  while (g(lo) > 0 && lo > -1e6) lo *= 2;
-  while (g(hi) < 0 && hi < 1e6) hi *= 2;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid == lo || mid == hi) break;
-    if (g(mid) > 0) hi = mid;
-    else lo = mid;
-  }
-  const double s = 0.5 * (lo + hi);
-  double den = 0.0;
-  for (int i = 0; i < K; ++i) den += a[i] * std::exp((F - i) * s);
-  for (int i = 0; i < K; ++i) sig[i] = std::sqrt(std::exp((F - i) * s) / den);
-  return GPE_OK;
-}
-
-// Closed-form retraction (Sec. 6.3, eq. retract3).
-static gpe_status sigma_closed(gpe_handle* h, const double* a, double* sig) {
-  const int K = h->K, F = h->F;
-  const double M = h->M;
-  double ww = 0, wg = 0, wg2 = 0;
-  for (int i = 0; i < K; ++i) {
-    const double l = F - i;
-    ww += a[i];
-    wg += l * a[i];
-    wg2 += l * l * a[i];
-  }
-  const double den = ww * wg2 - wg * wg;
-  auto num = [&](double l) { return wg2 - (M + l) * wg + M * l * ww; };
-  if (!(num(F) > 0 && num(-F) > 0 && den > 0)) return fail(h, GPE_EDOMAIN, "retraction argument outside S");
-  for (int i = 0; i < K; ++i) sig[i] = std::sqrt(num(F - i) / den);
-  return GPE_OK;
-}
-
 gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* sig) {
+  int r;
   switch (kind) {
-    case GPE_R1_PROJECTIVE: return sigma_projective(h, a, sig);
-    case GPE_R2_ORTHOGONAL: return sigma_orthogonal(h, a, sig);
-    case GPE_R3_CLOSED: return sigma_closed(h, a, sig);
+    case GPE_R1_PROJECTIVE: r = sigma_projective(h->F, h->M, a, sig); break;
+    case GPE_R2_ORTHOGONAL: r = sigma_orthogonal(h->F, h->M, a, sig); break;
+    case GPE_R3_CLOSED: r = sigma_closed(h->F, h->M, a, sig); break;
     default: return fail(h, GPE_EINVAL, "unknown retraction kind");
   }
+  if (r != SIGMA_OK)
+    return fail(h, GPE_EDOMAIN, kind == GPE_R3_CLOSED ? "retraction argument outside S"
+                                                      : "retraction argument outside Omega");
+  return GPE_OK;
 }
 
 gpe_status retract_sigma_at(gpe_handle* h, const RetractNorms& rn, double t, int kind, double* sig) {
@@ -557,11 +469,6 @@ using namespace gpe;
 
 // ----------------------------------------------------------------- C ABI
 
-static bool factors_23(int n) {
-  while (n % 2 == 0) n /= 2;
-  while (n % 3 == 0) n /= 3;
-  return n == 1;
-}
 
 extern "C" {
 
@@ -600,6 +507,8 @@ void gpe_solve_opts_default(gpe_solve_opts* o) {
   o->polish_tol = 0.0;
   o->polish_window = 0;
   o->cg_per_digit = 80.0;
+  o->trace = nullptr;
+  o->trace_cap = 0;
 }
 
 const char* gpe_last_error(const gpe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
@@ -628,10 +537,10 @@ gpe_status gpe_destroy(gpe_handle* h) {
   return GPE_OK;
 }
 
-gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision, void* stream, gpe_handle** out) {
+gpe_status gpe_create(const gpe_problem* pr, const double* V, int precision, void* stream, gpe_handle** out) {
   if (!out) return fail(nullptr, GPE_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!pr || !V_host) return fail(nullptr, GPE_EINVAL, "problem or potential is NULL");
+  if (!pr || !V) return fail(nullptr, GPE_EINVAL, "problem or potential is NULL");
   if (pr->F < 1 || pr->F > 3) return fail(nullptr, GPE_EINVAL, "F must be 1, 2 or 3");
   if (pr->dim < 1 || pr->dim > 3) return fail(nullptr, GPE_EINVAL, "dim must be 1, 2 or 3");
   if (precision != GPE_FP64 && precision != GPE_MIXED) return fail(nullptr, GPE_EINVAL, "bad precision");
@@ -639,9 +548,9 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
   if (pr->M < 0) return fail(nullptr, GPE_EINVAL, "M < 0: reverse the component order and pass -M");
   for (int a = 0; a < pr->dim; ++a) {
     const int n = pr->n[a];
-    if (n < 4 || n % 2 || !factors_23(n) || !lap_size_supported(n))
+    if (!lap_size_supported(n))
       return fail(nullptr, GPE_EINVAL, "n[" + std::to_string(a) + "] = " + std::to_string(n) +
-                                           " unsupported (even, factors 2 and 3 only, 4..512)");
+                                           " unsupported (2^k or 3*2^k, 4..512)");
     if (!(pr->hi[a] > pr->lo[a])) return fail(nullptr, GPE_EINVAL, "empty box");
   }
   gpe_handle* h = new gpe_handle();
@@ -667,8 +576,30 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V_host, int precision
     h->h *= (pr->hi[a] - pr->lo[a]) / pr->n[a];
   }
   h->nel = h->npts * h->K;
-  h->Vhost.assign(V_host, V_host + h->npts);
   (void)hipGetDevice(&h->device);
+  {
+    // V may live in host or device memory: a device (or managed) pointer is
+    // copied to the host mirror first; anything else is read as host memory
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, V) == hipSuccess)
+      on_device = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+    else
+      (void)hipGetLastError();
+    h->Vhost.resize(h->npts);
+    if (on_device) {
+      const hipError_t ev = hipMemcpy(h->Vhost.data(), V, h->npts * sizeof(double), hipMemcpyDeviceToHost);
+      if (ev != hipSuccess) {
+        hip_fail(h, ev, "copy of the device potential");
+        g_create_error = h->err;
+        delete h;
+        return GPE_EHIP;
+      }
+    } else {
+      std::memcpy(h->Vhost.data(), V, h->npts * sizeof(double));
+    }
+  }
+  const double* V_host = h->Vhost.data();
 
   // pointwise constants
   for (int i = 0; i < 7; ++i) {
@@ -879,6 +810,22 @@ gpe_status gpe_schedule(const gpe_handle* h, int* xpass_variant, float* variant_
   if (xpass_variant) *xpass_variant = h->xvar;
   for (int v = 0; v < nvariants && v < 3; ++v)
     if (variant_us) variant_us[v] = h->xvar_us[v];
+  return GPE_OK;
+}
+
+gpe_status gpe_set_schedule(gpe_handle* h, int xpass_variant) {
+  if (!h) return fail(nullptr, GPE_EINVAL, "NULL handle");
+  const int nv = xpass_variants(h->n[0]);
+  if (xpass_variant < 0 || xpass_variant >= nv)
+    return fail(h, GPE_EINVAL, "x-pass variant " + std::to_string(xpass_variant) + " out of range: this grid has " +
+                                   std::to_string(nv));
+  h->xvar = xpass_variant;
+  return GPE_OK;
+}
+
+gpe_status gpe_schedule_count(const gpe_handle* h, int* nvariants) {
+  if (!h || !nvariants) return fail(nullptr, GPE_EINVAL, "NULL argument");
+  *nvariants = xpass_variants(h->n[0]);
   return GPE_OK;
 }
 

@@ -150,7 +150,8 @@ gpe_status adopt_point(gpe_handle* h);
 // HVP at the set point in the work precision; if kappa != null also
 // returns <Z, HZ> and ||Z||^2 (synchronises).
 PwParams hvp_params(const gpe_handle* h, bool riemannian, double sigma);
-gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, bool cg);
+gpe_status hvp_enq(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, bool cg,
+                   bool kappa = true);
 gpe_status hvp_read(gpe_handle* h, double* kappa, double* zz);
 gpe_status hvp(gpe_handle* h, const void* Z, void* HZ, bool riemannian, double sigma, double* kappa,
                double* zz);

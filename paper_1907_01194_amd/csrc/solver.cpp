@@ -245,6 +245,17 @@ void push_adopt(Ctx& c) {
   } while (0)
 #define ROUND co_await Round{}
 
+// One row of the optional solve trace (gpe_solve_opts.trace, GPE_TRACE_COLS columns).
+static void trace_row(const gpe_solve_opts* o, gpe_solve_stats* st, double t, double E, double gn, double sigma,
+                      double ratio, int cg, int reason, double step, int accepted) {
+  if (!o->trace || st->trace_len >= o->trace_cap) return;
+  double* r = o->trace + (size_t)st->trace_len * GPE_TRACE_COLS;
+  const double v[GPE_TRACE_COLS] = {t, E, gn, (double)st->hvp_calls, sigma, ratio, (double)cg, (double)reason,
+                                    step, (double)accepted};
+  for (int i = 0; i < GPE_TRACE_COLS; ++i) r[i] = v[i];
+  st->trace_len++;
+}
+
 SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats* st) {
   gpe_handle* h = c.h;
   Clock clk;
@@ -341,6 +352,7 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
     }
   }
   st->t_rgbb = crg.sec();
+  trace_row(o, st, clk.sec(), E, gn, 0.0, NAN, 0, -1, 0.0, 1);
 
   // ------------------------------------------------------------ ARNT
   Clock carnt;
@@ -527,6 +539,7 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
       shat *= o->gamma2;
     }
     if (sigma_est >= 0 && gn > 0) shat = std::fmax(shat * gn, sigma_est) / gn;
+    trace_row(o, st, clk.sec(), E, gn, sigma, ratio, it, cs.reason, t, ratio >= o->eta1 ? 1 : 0);
   }
   st->t_arnt = carnt.sec();
   if (h->polish) {   // leave the handle's HVPs in its own precision at the final point
@@ -616,6 +629,8 @@ gpe_status newton_solve(gpe_handle* h, void* Xio, const gpe_solve_opts* o, gpe_s
     gpe_solve_opts oc = *o;
     oc.tol = o->mg_coarse_tol;
     oc.mg_levels = 0;
+    oc.trace = nullptr;   // the trace follows the finest mesh only
+    oc.trace_cap = 0;
     if (o->time_limit > 0) oc.time_limit = std::fmax(o->time_limit - clk.sec(), 1e-3);
     gpe_solve_stats sc;
     std::memset(&sc, 0, sizeof(sc));

@@ -72,3 +72,60 @@ def test_struct_layout_matches_c(tmp_path):
         assert int(got[sname]) == ctypes.sizeof(cls), sname
         for f, _ in cls._fields_:
             assert int(got[sname + "." + f]) == getattr(cls, f).offset, (sname, f)
+
+
+def _bad_problem(**kw):
+    pr = binding.gpe_problem()
+    pr.F, pr.dim = 2, 2
+    for a in range(3):
+        pr.n[a], pr.lo[a], pr.hi[a] = (16, -4.0, 4.0) if a < 2 else (1, 0.0, 1.0)
+    pr.beta[0], pr.beta[1], pr.beta[2] = 100.0, 1.0, -1.0
+    pr.M = 0.3
+    for k, v in kw.items():
+        if k in ("n", "lo", "hi"):
+            for a, x in enumerate(v):
+                getattr(pr, k)[a] = x
+        else:
+            setattr(pr, k, v)
+    return pr
+
+
+@pytest.mark.parametrize("what,kw", [
+    ("|M| = F", dict(M=2.0)), ("|M| > F", dict(M=3.5)), ("M < 0", dict(M=-0.3)),
+    ("F = 0", dict(F=0)), ("F = 4", dict(F=4)), ("dim = 0", dict(dim=0)), ("dim = 4", dict(dim=4)),
+    ("odd n", dict(n=(15, 16, 1))), ("n = 36 (2^2 3^2)", dict(n=(36, 16, 1))), ("n = 10", dict(n=(16, 10, 1))),
+    ("n = 2", dict(n=(2, 16, 1))), ("n = 1024", dict(n=(1024, 16, 1))), ("empty box", dict(hi=(-4.0, 4.0, 1.0))),
+])
+def test_create_rejects_invalid_problems(lib, what, kw):
+    """gpe_create validates the problem before touching the device (Sec. 2
+    constraint |M| < F, Sec. 3 even n; the library's size list), so these run
+    without a GPU: GPE_EINVAL, NULL handle, a message naming the fault."""
+    pr = _bad_problem(**kw)
+    V = (ctypes.c_double * (16 * 16 * 36))()
+    h = ctypes.c_void_p(12345)
+    st = lib.gpe_create(ctypes.byref(pr), ctypes.cast(V, ctypes.c_void_p), binding.FP64, None, ctypes.byref(h))
+    assert st == 1, what
+    assert h.value is None
+    assert lib.gpe_last_error(None), what
+
+
+def test_create_rejects_null_arguments(lib):
+    pr = _bad_problem()
+    h = ctypes.c_void_p()
+    assert lib.gpe_create(ctypes.byref(pr), None, binding.FP64, None, ctypes.byref(h)) == 1
+    assert b"NULL" in lib.gpe_last_error(None)
+    V = (ctypes.c_double * 256)()
+    assert lib.gpe_create(None, ctypes.cast(V, ctypes.c_void_p), binding.FP64, None, ctypes.byref(h)) == 1
+    assert lib.gpe_create(ctypes.byref(pr), ctypes.cast(V, ctypes.c_void_p), 7, None, ctypes.byref(h)) == 1
+    assert lib.gpe_create(ctypes.byref(pr), ctypes.cast(V, ctypes.c_void_p), binding.FP64, None, None) == 1
+
+
+def test_calls_reject_null_handles(lib):
+    """Entry points given a NULL handle or NULL buffers fail with GPE_EINVAL
+    (no device access happens)."""
+    E = ctypes.c_double()
+    assert lib.gpe_energy(None, None, ctypes.byref(E)) == 1
+    assert lib.gpe_set_schedule(None, 0) == 1
+    n = ctypes.c_int()
+    assert lib.gpe_schedule_count(None, ctypes.byref(n)) == 1
+    assert lib.gpe_destroy(None) == 0

@@ -4,8 +4,10 @@ Per call: energy (Sec. 3), Euclidean and Riemannian gradient (Sec. 3, Sec. 4),
 Euclidean and Riemannian Hessian-vector products (Sec. 3, Lemma 4.2) and the
 three retractions (Sec. 6), on seeded inputs, for F = 1, 2, 3 in 1D/2D/3D on
 grids that span several workgroups with ragged tails, plus the full-size
-spin-3 128^3 workload.  Tolerances: FP64 1e-10 relative on energies (the
-stated bar) and 1e-11 relative 2-norm on fields; mixed (c64) HVPs 1e-5.
+spin-3 128^3 workload with every x-pass schedule variant forced, and the
+spin-2 2D 256^2 workload.  Tolerances: FP64 1e-10 relative on energies (the
+stated bar); fields 1e-11 (FP64) and 1e-5 (mixed c64 HVPs) both as a relative
+2-norm and as every component's max|error| / max|reference|.
 """
 import numpy as np
 import pytest
@@ -46,7 +48,7 @@ def setup_case(F, n, seed=0, precision="fp64", p=0.0, q=0.0):
 
 @pytest.mark.parametrize("case", CASES, ids=ids)
 def test_energy_grad_parity(torch, case):
-    from gpu_util import dev, host, relnorm
+    from gpu_util import dev, host, assert_field
     F, n = case
     print("energy/grad parity", case, flush=True)
     spec, prob, u, gp = setup_case(F, n, p=0.1, q=0.05)
@@ -55,30 +57,30 @@ def test_energy_grad_parity(torch, case):
     E_or = oracle.energy(prob, u)
     assert abs(E - E_or) <= 1e-10 * abs(E_or)
     G, E2, gn = gp.grad(X, riemannian=False)
-    assert relnorm(host(G), oracle.grad(prob, u)) <= 1e-11
+    assert_field(host(G), oracle.grad(prob, u), 1e-11, "grad")
     assert abs(gn - np.linalg.norm(oracle.grad(prob, u))) <= 1e-11 * gn
     gR, E3, gnR = gp.grad(X, riemannian=True)
     g_or = oracle.rgrad(prob, u)[0]
-    assert relnorm(host(gR), g_or) <= 1e-11
+    assert_field(host(gR), g_or, 1e-11, "rgrad")
     assert abs(gnR - np.sqrt(oracle.inner(g_or, g_or))) <= 1e-11 * gnR
     assert abs(E2 - E_or) <= 1e-10 * abs(E_or) and abs(E3 - E_or) <= 1e-10 * abs(E_or)
 
 
 @pytest.mark.parametrize("case", CASES, ids=ids)
 def test_hvp_parity(torch, case):
-    from gpu_util import dev, host, relnorm
+    from gpu_util import dev, host, assert_field
     F, n = case
     print("hvp parity", case, flush=True)
     spec, prob, u, gp = setup_case(F, n, seed=1, p=-0.2, q=0.1)
     Z = W.random_direction(spec, 11) * 1e-2
     gp.set_point(dev(u))
     H = gp.hvp(dev(Z), riemannian=False)
-    assert relnorm(host(H), oracle.hvp(prob, u, Z)) <= 1e-11
+    assert_field(host(H), oracle.hvp(prob, u, Z), 1e-11, "hvp")
     xi = oracle.project(prob, u, Z)
     sigma = 0.3
     HR = gp.hvp(dev(xi), riemannian=True, sigma=sigma)
     HR_or = oracle.rhess(prob, u, xi, sigma=sigma)
-    assert relnorm(host(HR), HR_or) <= 1e-11
+    assert_field(host(HR), HR_or, 1e-11, "rhess")
     HR2, kappa = gp.hvp_dot(dev(xi), sigma)
     k_or = oracle.inner(xi, HR_or)
     assert abs(kappa - k_or) <= 1e-10 * abs(k_or) + 1e-13
@@ -86,22 +88,22 @@ def test_hvp_parity(torch, case):
 
 @pytest.mark.parametrize("case", [(1, (24,)), (2, (12, 16)), (3, (8, 12, 16)), (3, (24, 32, 12))], ids=ids)
 def test_hvp_mixed_precision(torch, case):
-    from gpu_util import dev, host, relnorm
+    from gpu_util import dev, host, assert_field
     F, n = case
     print("hvp mixed", case, flush=True)
     spec, prob, u, gp = setup_case(F, n, seed=2, precision="mixed")
     xi = oracle.project(prob, u, W.random_direction(spec, 12))
     gp.set_point(dev(u))
     H = gp.hvp(dev(xi, torch.complex64), riemannian=False)
-    assert relnorm(host(H), oracle.hvp(prob, u, xi)) <= 1e-5
+    assert_field(host(H), oracle.hvp(prob, u, xi), 1e-5, "hvp mixed")
     HR = gp.hvp(dev(xi, torch.complex64), riemannian=True, sigma=0.1)
-    assert relnorm(host(HR), oracle.rhess(prob, u, xi, sigma=0.1)) <= 1e-5
+    assert_field(host(HR), oracle.rhess(prob, u, xi, sigma=0.1), 1e-5, "rhess mixed")
 
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
 @pytest.mark.parametrize("case", [(1, (24,)), (2, (12, 16)), (3, (8, 12, 16))], ids=ids)
 def test_retraction_parity(torch, case, kind):
-    from gpu_util import dev, host, relnorm
+    from gpu_util import dev, host, assert_field
     F, n = case
     print("retract", case, kind, flush=True)
     spec, prob, u, gp = setup_case(F, n, seed=3)
@@ -110,7 +112,7 @@ def test_retraction_parity(torch, case, kind):
     for t in (1.0, 0.3, 0.0):
         Z = gp.retract(dev(u), dev(xi), t, kind)
         ref = oracle.retract(prob, u, xi, t, kind)
-        assert relnorm(host(Z), ref) <= 1e-12
+        assert_field(host(Z), ref, 1e-12, "retract")
         mass, mag = gp.constraints(Z)
         assert abs(mass - 1) <= 1e-12 and abs(mag - spec.M) <= 1e-12
 
@@ -134,12 +136,123 @@ def test_hvp_requires_set_point(torch):
     assert e.value.status == 1
 
 
-def test_full_size_spin3_128(torch):
-    """spin-3 128^3 workload (the benchmark's configuration): energy, Riemannian
-    gradient and Riemannian HVP against the oracle, FP64 and mixed."""
+@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("case", [(1, (24,)), (2, (12, 16)), (3, (8, 12, 16))], ids=ids)
+def test_retraction_magnetization_zero(torch, case, kind):
+    """M = 0 (the l = M term drops out of h1 for integer M, Sec. 6.1)."""
     from paper_1907_01194_amd.binding import Problem
-    from gpu_util import dev, host, relnorm
-    print("full size spin-3 128^3", flush=True)
+    from gpu_util import dev, host, assert_field
+    F, n = case
+    print("retract M=0", case, kind, flush=True)
+    spec = small_spec(F, n, M=0.0)
+    prob = oracle_problem(spec)
+    u = oracle.retraction.psi(prob, W.noisy_envelope_state(spec, 21, (0.2,) * len(n)), 1)
+    xi = oracle.project(prob, u, W.random_direction(spec, 22))
+    xi *= 0.3 / np.sqrt(oracle.inner(xi, xi))
+    gp = Problem(spec, "fp64")
+    for t in (1.0, 0.25, 0.0):
+        Z = gp.retract(dev(u), dev(xi), t, kind)
+        assert_field(host(Z), oracle.retract(prob, u, xi, t, kind), 1e-12, "retract M=0")
+        mass, mag = gp.constraints(Z)
+        assert abs(mass - 1) <= 1e-12 and abs(mag) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("F,zero", [(1, (1,)), (2, (0, 3)), (3, (1, 2, 6))], ids=["F1", "F2", "F3"])
+def test_retraction_zero_components(torch, F, zero, kind):
+    """Arguments with empty components (a_l = 0): R1 restricts to [f1, f2],
+    R2 and R3 scale an empty component by any factor."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev, host, assert_field
+    print("retract zero components", F, zero, kind, flush=True)
+    n = (12, 10)
+    spec = small_spec(F, n, M=0.3)
+    prob = oracle_problem(spec)
+    w = W.noisy_envelope_state(spec, 31 + F, (0.2, 0.2))
+    w[list(zero)] = 0.0
+    u = oracle.retraction.psi(prob, w, 1)
+    Zr = W.random_direction(spec, 32 + F)
+    Zr[list(zero)] = 0.0
+    xi = oracle.project(prob, u, Zr)
+    xi *= 0.2 / np.sqrt(oracle.inner(xi, xi))
+    assert np.all(xi[list(zero)] == 0)
+    gp = Problem(spec, "fp64")
+    for t in (1.0, 0.5, 0.0):
+        try:
+            ref = oracle.retract(prob, u, xi, t, kind)
+        except ValueError:          # outside S (closed form): the library must say so too
+            from paper_1907_01194_amd.binding import GpeError
+            with pytest.raises(GpeError) as e:
+                gp.retract(dev(u), dev(xi), t, kind)
+            assert e.value.status == 2
+            continue
+        Z = gp.retract(dev(u), dev(xi), t, kind)
+        got = host(Z)
+        assert np.all(got[list(zero)] == 0)
+        assert_field(got, ref, 1e-12, "retract zero components")
+        mass, mag = gp.constraints(Z)
+        assert abs(mass - 1) <= 1e-12 and abs(mag - spec.M) <= 1e-12
+
+
+def test_failure_paths(torch):
+    """Through the C ABI: NaN input (GPE_ENUMERIC), a point whose projection
+    is degenerate (GPE_EDEGEN: all mass in one component), a schedule variant
+    out of range (GPE_EINVAL)."""
+    from paper_1907_01194_amd.binding import GpeError
+    from gpu_util import dev
+    print("failure paths", flush=True)
+    spec, prob, u, gp = setup_case(2, (16, 12), seed=6)
+    bad = u.copy()
+    bad[1, 3, 4] = np.nan
+    with pytest.raises(GpeError) as e:
+        gp.energy(dev(bad))
+    assert e.value.status == 4
+    with pytest.raises(GpeError) as e:
+        gp.grad(dev(bad), riemannian=True)
+    assert e.value.status == 4
+    one = np.zeros_like(u)
+    one[2] = u[2] / np.sqrt(oracle.inner(u[2], u[2]))     # l = 0 only: u^T Gamma^2 u = (u^T Gamma u)^2 = 0
+    with pytest.raises(GpeError) as e:
+        gp.grad(dev(one), riemannian=True)
+    assert e.value.status == 3
+    with pytest.raises(GpeError) as e:
+        gp.set_point(dev(one))
+    assert e.value.status == 3
+    with pytest.raises(GpeError) as e:
+        gp.set_schedule(gp.schedule_count())
+    assert e.value.status == 1
+    # the handle still works after every error
+    E = gp.energy(dev(u))
+    assert abs(E - oracle.energy(prob, u)) <= 1e-10 * abs(E)
+
+
+def test_potential_on_device(torch):
+    """gpe_create takes V in device memory as well as host memory."""
+    import ctypes
+    from paper_1907_01194_amd import binding as B
+    from gpu_util import dev
+    print("device potential", flush=True)
+    spec, prob, u, gp = setup_case(3, (16, 12, 8), seed=7)
+    Vd = torch.from_numpy(np.ascontiguousarray(spec.V)).cuda()
+    h = ctypes.c_void_p()
+    pr = B.problem_struct(spec)
+    st = B.lib().gpe_create(ctypes.byref(pr), ctypes.c_void_p(Vd.data_ptr()), B.FP64,
+                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+    assert st == 0, B.lib().gpe_last_error(None)
+    del Vd
+    torch.cuda.synchronize()
+    X = dev(u)
+    E = ctypes.c_double()
+    assert B.lib().gpe_energy(h, ctypes.c_void_p(X.data_ptr()), ctypes.byref(E)) == 0
+    B.lib().gpe_destroy(h)
+    assert E.value == gp.energy(X)
+
+
+# ---------------------------------------------------------------- full-size workloads
+
+@pytest.fixture(scope="module")
+def spin3_full():
+    """spin-3 128^3 (the benchmark's configuration) and its oracle values."""
     spec = W.spin3_3d(128)
     prob = oracle_problem(spec)
     u = oracle.retraction.psi(prob, W.initial_state(spec, 3), 1)
@@ -148,15 +261,67 @@ def test_full_size_spin3_128(torch):
     g_or, G_or, ag, bg = oracle.rgrad(prob, u)
     E_or = oracle.energy(prob, u)
     H_or = oracle.rhess(prob, u, xi, ag, bg, 1e-2)
-    for prec, tol in (("fp64", 1e-11), ("mixed", 1e-5)):
-        gp = Problem(spec, prec)
-        X = dev(u)
-        assert abs(gp.energy(X) - E_or) <= 1e-10 * abs(E_or)
-        gR, E, gn = gp.grad(X, riemannian=True)
-        assert relnorm(host(gR), g_or) <= 1e-11
-        gp.set_point(X)
-        Z = dev(xi, gp.work_dtype)
-        HR = gp.hvp(Z, riemannian=True, sigma=1e-2)
-        assert relnorm(host(HR), H_or) <= tol, prec
-        del gp
-        torch.cuda.empty_cache()
+    return spec, u, xi, E_or, g_or, H_or
+
+
+@pytest.mark.parametrize("prec,variant", [(p, v) for p in ("fp64", "mixed") for v in (0, 1, 2)])
+def test_full_size_spin3_128(torch, spin3_full, prec, variant):
+    """spin-3 128^3: energy, Riemannian gradient and Riemannian HVP against the
+    oracle with each x-pass schedule variant forced, FP64 and mixed."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev, host, assert_field
+    print("full size spin-3 128^3", prec, "variant", variant, flush=True)
+    spec, u, xi, E_or, g_or, H_or = spin3_full
+    gp = Problem(spec, prec)
+    assert gp.schedule_count() == 3
+    gp.set_schedule(variant)
+    assert gp.schedule()[0] == variant
+    X = dev(u)
+    assert abs(gp.energy(X) - E_or) <= 1e-10 * abs(E_or)
+    gR, E, gn = gp.grad(X, riemannian=True)
+    assert_field(host(gR), g_or, 1e-11, "rgrad")
+    gp.set_point(X)
+    HR = gp.hvp(dev(xi, gp.work_dtype), riemannian=True, sigma=1e-2)
+    assert_field(host(HR), H_or, 1e-11 if prec == "fp64" else 1e-5, "rhess %s variant %d" % (prec, variant))
+    gp.close()
+    del gp, X, gR, HR
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def spin2_full():
+    """spin-2 2D 256^2 with its own physics (lattice V, beta = (100, 1, -1), M = 0.3)."""
+    spec = W.spin2_2d()
+    prob = oracle_problem(spec)
+    u = oracle.retraction.psi(prob, W.initial_state(spec, 2), 1)
+    Z = W.random_direction(spec, 202) * 1e-2
+    xi = oracle.project(prob, u, Z)
+    g_or, G_or, ag, bg = oracle.rgrad(prob, u)
+    return (spec, u, Z, xi, oracle.energy(prob, u), G_or, g_or, oracle.hvp(prob, u, Z),
+            oracle.rhess(prob, u, xi, ag, bg, 0.05))
+
+
+@pytest.mark.parametrize("prec,variant", [(p, v) for p in ("fp64", "mixed") for v in (0, 1, 2)])
+def test_full_size_spin2_256(torch, spin2_full, prec, variant):
+    """spin-2 2D 256^2: energy, Euclidean and Riemannian gradient, Euclidean and
+    Riemannian HVP with each x-pass schedule variant forced."""
+    from paper_1907_01194_amd.binding import Problem
+    from gpu_util import dev, host, assert_field
+    print("full size spin-2 256^2", prec, "variant", variant, flush=True)
+    spec, u, Z, xi, E_or, G_or, g_or, H_or, HR_or = spin2_full
+    gp = Problem(spec, prec)
+    assert gp.schedule_count() == 3
+    gp.set_schedule(variant)
+    X = dev(u)
+    E = gp.energy(X)
+    assert abs(E - E_or) <= 1e-10 * abs(E_or)
+    G, _, _ = gp.grad(X, riemannian=False)
+    assert_field(host(G), G_or, 1e-11, "grad")
+    gR, _, _ = gp.grad(X, riemannian=True)
+    assert_field(host(gR), g_or, 1e-11, "rgrad")
+    gp.set_point(X)
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    H = gp.hvp(dev(Z, gp.work_dtype), riemannian=False)
+    assert_field(host(H), H_or, tol, "hvp %s variant %d" % (prec, variant))
+    HR = gp.hvp(dev(xi, gp.work_dtype), riemannian=True, sigma=0.05)
+    assert_field(host(HR), HR_or, tol, "rhess %s variant %d" % (prec, variant))

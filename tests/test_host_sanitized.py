@@ -1,0 +1,122 @@
+"""Host code of the library built with AddressSanitizer and
+UndefinedBehaviorSanitizer on the CPU (g++, no GPU code): the scalar solves of
+the three retractions (Sec. 6.1 projective, 6.2 orthogonal, 6.3 closed form),
+checked against the oracle's on random component norms that include empty
+components, M = 0 and points outside the retractions' domains."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1907_01194_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("san") / "sigma_driver")
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+    cmd = [gxx, "-std=c++17", "-O1", "-g"] + san + ["-I", CSRC,
+           os.path.join(ROOT, "tests", "native", "sigma_driver.cpp"), os.path.join(CSRC, "retract_scalar.cpp"),
+           "-o", exe]
+    subprocess.run(cmd, check=True)
+    return exe
+
+
+def cases(seed=0, count=400):
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(count):
+        F = int(rng.integers(1, 4))
+        K = 2 * F + 1
+        M = 0.0 if c % 4 == 0 else float(rng.uniform(0, F * 0.95))
+        a = rng.random(K) ** 3
+        nzero = int(rng.integers(0, K))            # empty components
+        a[rng.choice(K, nzero, replace=False)] = 0.0
+        if c % 7 == 0:
+            a *= 10.0 ** rng.uniform(-12, 6)       # far from unit mass
+        kind = 1 + c % 3
+        out.append((kind, F, M, a))
+    return out
+
+
+def oracle_sigma(kind, F, M, a):
+    prob = make_problem(F, (4,), (0.0,), (1.0,), np.zeros(4), (0.0,) * 4, M)
+    fn = {1: oracle.retraction.sigma_r1, 2: oracle.retraction.sigma_r2, 3: oracle.retraction.sigma_r3}[kind]
+    try:
+        return 0, fn(prob, a)[0]
+    except ValueError:
+        return 2, None
+
+
+def test_sanitized_scalar_solves_match_oracle(driver):
+    cs = cases()
+    text = "".join("%d %d %.17g %s\n" % (k, F, M, " ".join("%.17g" % v for v in a)) for k, F, M, a in cs)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([driver], input=text, capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
+    lines = r.stdout.splitlines()
+    assert len(lines) == len(cs)
+    ndomain = 0
+    for (kind, F, M, a), line in zip(cs, lines):
+        f = line.split()
+        st = int(f[0])
+        sig = np.array([float(v) for v in f[1:]])
+        ost, osig = oracle_sigma(kind, F, M, a)
+        assert st == ost, (kind, F, M, a)
+        if st:
+            ndomain += 1
+            continue
+        assert np.all(np.isfinite(sig))
+        # the retracted norms meet both constraints
+        l = np.arange(F, -F - 1, -1)
+        mass = np.sum(sig ** 2 * a)
+        assert abs(mass - 1) <= 1e-12 and abs(np.sum(l * sig ** 2 * a) - M) <= 1e-12 * max(1, F)
+        # factors of empty components do not matter; compare the others
+        nz = a > 0
+        assert np.max(np.abs(sig[nz] - osig[nz]) / np.abs(osig[nz])) <= 1e-10, (kind, F, M, a)
+    assert 0 < ndomain < len(cs)
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_sanitized_scalar_solves_extreme_norms(driver, kind):
+    """Component norms over 200-300 decades: the factors stay finite and the
+    retracted norms meet both constraints (no oracle: numpy's plain forms
+    overflow there).  The orthogonal factors are formed in the log domain, the
+    closed form's sums are regrouped so that no large terms cancel, and the
+    projective zero is sought as an offset from the pole it lies next to."""
+    decades = {1: 100, 2: 150, 3: 100}[kind]
+    rng = np.random.default_rng(11 + kind)
+    cs = []
+    for c in range(120):
+        F = int(rng.integers(1, 4))
+        K = 2 * F + 1
+        M = 0.0 if c % 3 == 0 else float(rng.uniform(0, 0.9 * F))
+        a = 10.0 ** rng.uniform(-decades, decades, K)
+        a[rng.random(K) < 0.3] = 0.0
+        cs.append((kind, F, M, a))
+    text = "".join("%d %d %.17g %s\n" % (k, F, M, " ".join("%.17g" % v for v in a)) for k, F, M, a in cs)
+    r = subprocess.run([driver], input=text, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    nok = 0
+    for (k, F, M, a), line in zip(cs, r.stdout.splitlines()):
+        f = line.split()
+        if int(f[0]):
+            continue
+        nok += 1
+        sig = np.array([float(v) for v in f[1:]])
+        assert np.all(np.isfinite(sig)), (k, F, M, a)
+        l = np.arange(F, -F - 1, -1)
+        w = sig ** 2 * a
+        assert abs(w.sum() - 1) <= 1e-11 and abs(np.sum(l * w) - M) <= 1e-11 * F, (k, F, M, a, w)
+    assert nok > 10
