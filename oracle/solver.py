@@ -42,14 +42,18 @@ ends if no trial of a search can be retracted.  Thirty rejections
 in a row end
 the run unconverged.  sigma_hat never drops below 1e-8 (repeated very
 successful steps would otherwise drive it to underflow, after which the
-increases on rejection can no longer restore any regularisation).
+increases on rejection can no longer restore any regularisation).  The
+gradient given to the truncated CG is projected onto the tangent space twice
+(tangent_grad): with one projection its normal rounding noise, eps ||grad E||,
+bounds the CG residual from below and the CG breaks down once the residual
+tolerance ||grad||^2 falls under it.
 """
 
 from dataclasses import dataclass, field
 import numpy as np
 
 from .energy import energy, grad as egrad, hvp as ehvp, laplacian
-from .manifold import inner, rgrad, rhess
+from .manifold import inner, rgrad, rhess, project
 from .retraction import retract, psi
 
 
@@ -198,11 +202,24 @@ def tcg(prob, u, gR, ag, bg, sigma, opts, stats):
     return z, None, None, None
 
 
+def tangent_grad(prob, u, G):
+    """Riemannian gradient for the Newton subproblem: P_u applied twice.  One
+    projection of G leaves a normal component of the size of its rounding,
+    eps ||G||, and ||G|| stays O(E) at a critical point while ||grad|| -> 0; the
+    truncated CG cannot reduce a normal residual (its operator maps into the
+    tangent space), so that noise would bound the CG residual from below.
+    Projecting the (small) result again leaves eps ||grad||.  Returns
+    (grad, alpha_g, beta_g) with the multipliers of the first projection
+    (those of Lemma 4.2's Hessian)."""
+    gR, _, ag, bg = rgrad(prob, u, G)
+    return project(prob, u, gR), ag, bg
+
+
 def arnt(prob, u, opts, stats):
     """Modified adaptive regularized Newton method (Algorithm 1, second loop)."""
     eps = np.finfo(float).eps
     E, G = energy_grad(prob, u)
-    gR, G, ag, bg = rgrad(prob, u, G)
+    gR, ag, bg = tangent_grad(prob, u, G)
     gn = _norm(gR)
     shat = opts.sigma_hat0
     streak = 0
@@ -258,8 +275,8 @@ def arnt(prob, u, opts, stats):
                 ratio = dE / m
         stats.outer += 1
         if ratio >= opts.eta1:
-            u, E = z, Ez
-            gR, G, ag, bg = rgrad(prob, u, Gz)
+            u, E, G = z, Ez, Gz
+            gR, ag, bg = tangent_grad(prob, u, G)
             gn = _norm(gR)
             shat = max(shat * (opts.gamma0 if ratio >= opts.eta2 else opts.gamma1), opts.sigma_hat_min)
             streak = 0

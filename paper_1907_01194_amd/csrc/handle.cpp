@@ -93,7 +93,9 @@ gpe_status eval_enq(gpe_handle* h, const void* X, void* G, double* gram) {
 gpe_status eval_read(gpe_handle* h, bool grad, double* E, double* ag, double* bg) {
   const int nq = 1 + 2 * h->K;
   const double* r = h->hres;
-  GPE_TRY(finite(h, r, grad ? nq + 2 : 1, "the energy or gradient"));
+  // the reductions first; the multipliers after the degeneracy test (a
+  // singular Gram system gives NaN multipliers, which is GPE_EDEGEN)
+  GPE_TRY(finite(h, r, grad ? nq : 1, "the energy or gradient"));
   if (grad) {
     double a11 = 0, a12 = 0, a22 = 0;
     for (int i = 0; i < h->K; ++i) {
@@ -104,6 +106,7 @@ gpe_status eval_read(gpe_handle* h, bool grad, double* E, double* ag, double* bg
     }
     if (!(a11 * a22 - a12 * a12 > 0))
       return fail(h, GPE_EDEGEN, "degenerate point: u^T Gamma^2 u u^T u - (u^T Gamma u)^2 <= 0");
+    GPE_TRY(finite(h, r + nq, 2, "the gradient's multipliers"));
     if (ag) *ag = r[nq];
     if (bg) *bg = r[nq + 1];
   }
@@ -308,6 +311,23 @@ gpe_status retraction_sigma(gpe_handle* h, const double* a, int kind, double* si
   if (r != SIGMA_OK)
     return fail(h, GPE_EDOMAIN, kind == GPE_R3_CLOSED ? "retraction argument outside S"
                                                       : "retraction argument outside Omega");
+  return GPE_OK;
+}
+
+gpe_status proj_coeffs(gpe_handle* h, const RetractNorms& rn, double* alpha, double* beta) {
+  double a11 = 0, a12 = 0, a22 = 0, r1 = 0, r2 = 0;
+  for (int i = 0; i < h->K; ++i) {
+    const double l = h->F - i;
+    a11 += rn.uu[i];
+    a12 += l * rn.uu[i];
+    a22 += l * l * rn.uu[i];
+    r1 += rn.ux[i];
+    r2 += l * rn.ux[i];
+  }
+  const double det = a11 * a22 - a12 * a12;
+  if (!(det > 0)) return fail(h, GPE_EDEGEN, "degenerate Gram system in the projection");
+  *alpha = (a22 * r1 - a12 * r2) / det;
+  *beta = (a11 * r2 - a12 * r1) / det;
   return GPE_OK;
 }
 
@@ -783,18 +803,8 @@ gpe_status gpe_project(gpe_handle* h, const void* X, const void* W, void* out) {
   if (!h || !X || !W || !out) return fail(h, GPE_EINVAL, "NULL argument");
   RetractNorms rn;
   GPE_TRY(retract_norms(h, X, W, false, &rn));
-  double a11 = 0, a12 = 0, a22 = 0, r1 = 0, r2 = 0;
-  for (int i = 0; i < h->K; ++i) {
-    const double l = h->F - i;
-    a11 += rn.uu[i];
-    a12 += l * rn.uu[i];
-    a22 += l * l * rn.uu[i];
-    r1 += rn.ux[i];
-    r2 += l * rn.ux[i];
-  }
-  const double det = a11 * a22 - a12 * a12;
-  if (!(det > 0)) return fail(h, GPE_EDEGEN, "degenerate Gram system in the projection");
-  const double alpha = (a22 * r1 - a12 * r2) / det, beta = (a11 * r2 - a12 * r1) / det;
+  double alpha, beta;
+  GPE_TRY(proj_coeffs(h, rn, &alpha, &beta));
   double gn;
   GPE_TRY(project_grad(h, X, W, out, alpha, beta, &gn));
   return GPE_OK;

@@ -164,6 +164,9 @@ struct RetractNorms {
 gpe_status norms_enq(gpe_handle* h, const void* u, const void* xi, bool xi32);
 gpe_status norms_read(gpe_handle* h, bool has_xi, RetractNorms* rn);
 gpe_status retract_norms(gpe_handle* h, const void* u, const void* xi, bool xi32, RetractNorms* rn);
+// Coefficients (alpha, beta) of the projection of xi onto the tangent space at
+// u (Lemma 4.1 with the measured Gram system) from the norms of u and xi.
+gpe_status proj_coeffs(gpe_handle* h, const RetractNorms& rn, double* alpha, double* beta);
 // sigma_i of retraction `kind` at u + t xi, from the norms (host, FP64).
 gpe_status retract_sigma_at(gpe_handle* h, const RetractNorms& rn, double t, int kind, double* sig);
 gpe_status retract_apply(gpe_handle* h, const RetractNorms& rn, const void* u, const void* xi, bool xi32,

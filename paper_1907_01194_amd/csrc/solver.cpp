@@ -29,6 +29,11 @@
 //   * sigma_hat is kept >= sigma_hat_min (1e-8): a run of very successful
 //     steps would otherwise drive it to underflow, and the x10 increases on
 //     rejection could then never restore any regularisation.
+//   * the Riemannian gradient handed to the CG is projected twice: one
+//     projection of the Euclidean gradient (of norm O(E) at a critical point)
+//     leaves normal rounding noise eps ||grad E||, which the CG cannot reduce
+//     (its operator maps into the tangent space); once the residual tolerance
+//     ||grad||^2 falls below that noise the CG stalls and breaks down.
 // In a mixed-precision handle the CG vectors, the Hessian products and the
 // model evaluations are c64 with FP64 reductions; energies, gradients,
 // retractions and the ratio are FP64.
@@ -244,6 +249,23 @@ void push_adopt(Ctx& c) {
     if (s_ != GPE_OK) co_return s_;  \
   } while (0)
 #define ROUND co_await Round{}
+// Project gR onto the tangent space at u once more (in place) and read its
+// norm into gn.  One projection of G leaves a normal component of the size of
+// its rounding, eps ||G||, with ||G|| = O(E) at a critical point; the CG cannot
+// reduce a normal residual, so the second projection (leaving eps ||gR||)
+// keeps that noise below every residual tolerance.
+#define REPROJECT_GRAD()                                   \
+  do {                                                     \
+    RetractNorms rg_;                                      \
+    double a_, b_;                                         \
+    c.push(rq_norms(u, gR, false));                        \
+    ROUND;                                                 \
+    CO_TRY(norms_read(h, true, &rg_));                     \
+    CO_TRY(proj_coeffs(h, rg_, &a_, &b_));                 \
+    c.push(rq_pgrad(u, gR, gR, a_, b_));                   \
+    ROUND;                                                 \
+    CO_TRY(pgrad_read(h, &gn));                            \
+  } while (0)
 
 // One row of the optional solve trace (gpe_solve_opts.trace, GPE_TRACE_COLS columns).
 static void trace_row(const gpe_solve_opts* o, gpe_solve_stats* st, double t, double E, double gn, double sigma,
@@ -356,6 +378,7 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
 
   // ------------------------------------------------------------ ARNT
   Clock carnt;
+  REPROJECT_GRAD();
   h->E_pt = E;
   h->alpha_g = ag;
   h->beta_g = bg;
@@ -527,6 +550,7 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
       c.push(rq_pgrad(u, G, gR, ag, bg));
       ROUND;
       CO_TRY(pgrad_read(h, &gn));
+      REPROJECT_GRAD();
       h->E_pt = E;
       h->alpha_g = ag;
       h->beta_g = bg;
@@ -567,6 +591,7 @@ SolveTask solve_task(Ctx& c, void* Xio, const gpe_solve_opts* o, gpe_solve_stats
   co_return GPE_OK;
 }
 
+#undef REPROJECT_GRAD
 #undef CO_TRY
 #undef ROUND
 

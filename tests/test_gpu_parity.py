@@ -165,7 +165,7 @@ def test_retraction_zero_components(torch, F, zero, kind):
     from paper_1907_01194_amd.binding import Problem
     from gpu_util import dev, host, assert_field
     print("retract zero components", F, zero, kind, flush=True)
-    n = (12, 10)
+    n = (12, 16)
     spec = small_spec(F, n, M=0.3)
     prob = oracle_problem(spec)
     w = W.noisy_envelope_state(spec, 31 + F, (0.2, 0.2))

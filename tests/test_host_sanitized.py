@@ -24,7 +24,7 @@ def driver(tmp_path_factory):
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("san") / "sigma_driver")
     san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
-    cmd = [gxx, "-std=c++17", "-O1", "-g"] + san + ["-I", CSRC,
+    cmd = [gxx, "-std=c++17", "-O1", "-g"] + san + ["-iquote", CSRC,
            os.path.join(ROOT, "tests", "native", "sigma_driver.cpp"), os.path.join(CSRC, "retract_scalar.cpp"),
            "-o", exe]
     subprocess.run(cmd, check=True)
