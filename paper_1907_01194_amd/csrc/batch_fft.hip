@@ -88,13 +88,11 @@ template <int K, int VAR, int... Ns> struct XBatchGeo {
     ((m = XGeo<Ns, K, VAR>::THREADS > m ? XGeo<Ns, K, VAR>::THREADS : m), ...);
     return m;
   }();
-  static constexpr size_t LDS = [] {
+  template <typename T> static constexpr size_t lds_elems() {
     size_t m = 0;
-    ((m = (size_t)(Ns + XGeo<Ns, K, VAR>::LINES * (Ns + 1)) > m ? (size_t)(Ns + XGeo<Ns, K, VAR>::LINES * (Ns + 1))
-                                                                 : m),
-     ...);
+    ((m = XGeo<Ns, K, VAR>::template lds_elems<T>() > m ? XGeo<Ns, K, VAR>::template lds_elems<T>() : m), ...);
     return m;
-  }();
+  }
 };
 template <int K, int VAR> using XB = XBatchGeo<K, VAR, 16, 32, 64, 128, 256, 512>;
 
@@ -143,7 +141,7 @@ int xpass_batch_blocks(int n, int F, int var, size_t npts) {
 template <typename T, int F, int VAR>
 static hipError_t launch_xb(const XpassArgs<T>* args, const Span& sp, hipStream_t st) {
   using G = XB<2 * F + 1, VAR>;
-  const size_t lds = sizeof(c_t<T>) * G::LDS;
+  const size_t lds = sizeof(c_t<T>) * G::template lds_elems<T>();
   if (lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_batched_kernel<T, F, VAR>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

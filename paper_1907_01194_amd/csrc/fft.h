@@ -117,10 +117,19 @@ struct LineCtx {
   size_t goff;      // global element offset of this thread's line
   int gstride;      // element stride along the line in global memory
   int lbase;        // LDS element offset of this thread's line
-  int lstride;      // element stride along the line in LDS
+  int lstride;      // element stride along the line in LDS (unpadded layouts)
   int tl;           // thread index within the line
   bool valid;       // line exists
 };
+
+// Padded LDS layout of a line held contiguously: element j sits at
+// j + j/8.  The Stockham passes access a line at strides R (the first
+// pass's writes: 8 for radix 8) and 2rk (twiddles); one pad per 8 elements
+// spreads every such group of lanes over distinct banks, for 8- and
+// 16-byte elements alike.
+__host__ __device__ constexpr int pad8(int j) { return j + (j >> 3); }
+// LDS elements a padded line (or twiddle table) of length N occupies
+__host__ __device__ constexpr int padded_len(int N) { return N + (N >> 3) + 1; }
 
 // Epilogue of the last inverse pass: out = acc + val - pc * X (pc = 0: no projection).
 template <typename T> struct Epi {
@@ -129,10 +138,19 @@ template <typename T> struct Epi {
   T pc;
 };
 
-template <typename T, int N, int s, bool FWD, int SRC, int DST>
+// PAD: the line is contiguous in LDS in the padded layout (pad8), and so is
+// the twiddle table; otherwise element j of the line is at lbase + j lstride
+// and twiddle m at m.  raw (first pass only, may be null): the line as read
+// from global memory is also stored there, in the line's own LDS layout.
+template <bool PAD> __device__ __forceinline__ int lidx(const LineCtx& lc, int j) {
+  return PAD ? lc.lbase + pad8(j) : lc.lbase + j * lc.lstride;
+}
+
+template <typename T, int N, int s, bool FWD, int SRC, int DST, bool PAD>
 __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* lds,
                                       const c_t<T>* tw, c_t<T>* __restrict__ gout,
-                                      const Epi<T>& epi, const LineCtx& lc, T lamc, T invn, double& pars) {
+                                      const Epi<T>& epi, const LineCtx& lc, T lamc, T invn, double& pars,
+                                      c_t<T>* raw = nullptr) {
   using T2 = c_t<T>;
   constexpr RadixPlan P = Geo<N>::P;
   constexpr int R = P.r[s];
@@ -149,7 +167,8 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int j = b + r * B;
-        v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[lc.lbase + j * lc.lstride];
+        v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[lidx<PAD>(lc, j)];
+        if (SRC == SRC_GLOBAL && raw) raw[lidx<PAD>(lc, j)] = v[i][r];
       }
     }
   }
@@ -162,7 +181,8 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          T2 w = tw[(r * k * (N / (Ns * R))) % N];
+          const int m = (r * k * (N / (Ns * R))) % N;
+          T2 w = tw[PAD ? pad8(m) : m];
           if (!FWD) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -181,7 +201,7 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
           val = cscale(val, sc);
         }
         if (DST == DST_LDS) {
-          lds[lc.lbase + idx * lc.lstride] = val;
+          lds[lidx<PAD>(lc, idx)] = val;
         } else {
           const size_t g = lc.goff + (size_t)idx * lc.gstride;
           T2 o = epi.acc ? cadd(epi.acc[g], val) : val;
@@ -198,23 +218,24 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
   if (DST == DST_LDS) __syncthreads();
 }
 
-template <typename T, int N, int s>
+template <typename T, int N, int s, bool PAD = false>
 __device__ __forceinline__ void fwd_stages(const c_t<T>* gin, c_t<T>* lds, const c_t<T>* tw,
-                                           const LineCtx& lc, T lamc, T invn, double& pars) {
+                                           const LineCtx& lc, T lamc, T invn, double& pars,
+                                           c_t<T>* raw = nullptr) {
   constexpr int S = Geo<N>::P.S;
   const Epi<T> none{nullptr, nullptr, T(0)};
   if constexpr (s < S) {
     if constexpr (s == 0)
-      stage<T, N, 0, true, SRC_GLOBAL, DST_LDS>(gin, lds, tw, nullptr, none, lc, lamc, invn, pars);
+      stage<T, N, 0, true, SRC_GLOBAL, DST_LDS, PAD>(gin, lds, tw, nullptr, none, lc, lamc, invn, pars, raw);
     else
-      stage<T, N, s, true, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, lamc, invn, pars);
-    fwd_stages<T, N, s + 1>(gin, lds, tw, lc, lamc, invn, pars);
+      stage<T, N, s, true, SRC_LDS, DST_LDS, PAD>(nullptr, lds, tw, nullptr, none, lc, lamc, invn, pars);
+    fwd_stages<T, N, s + 1, PAD>(gin, lds, tw, lc, lamc, invn, pars);
   }
 }
 
 // LAST_TO_GLOBAL: the last inverse pass writes global memory through the
 // epilogue; otherwise it writes the result back to LDS.
-template <typename T, int N, int s, bool LAST_TO_GLOBAL>
+template <typename T, int N, int s, bool LAST_TO_GLOBAL, bool PAD = false>
 __device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>* gout, const Epi<T>& epi,
                                            const LineCtx& lc) {
   constexpr int S = Geo<N>::P.S;
@@ -222,10 +243,10 @@ __device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>
   double dummy = 0.0;
   if constexpr (s < S) {
     if constexpr (s == S - 1 && LAST_TO_GLOBAL)
-      stage<T, N, s, false, SRC_LDS, DST_GLOBAL>(nullptr, lds, tw, gout, epi, lc, T(0), T(0), dummy);
+      stage<T, N, s, false, SRC_LDS, DST_GLOBAL, PAD>(nullptr, lds, tw, gout, epi, lc, T(0), T(0), dummy);
     else
-      stage<T, N, s, false, SRC_LDS, DST_LDS>(nullptr, lds, tw, nullptr, none, lc, T(0), T(0), dummy);
-    inv_stages<T, N, s + 1, LAST_TO_GLOBAL>(lds, tw, gout, epi, lc);
+      stage<T, N, s, false, SRC_LDS, DST_LDS, PAD>(nullptr, lds, tw, nullptr, none, lc, T(0), T(0), dummy);
+    inv_stages<T, N, s + 1, LAST_TO_GLOBAL, PAD>(lds, tw, gout, epi, lc);
   }
 }
 
@@ -344,6 +365,16 @@ template <int N, int K, int VAR = 1> struct XGeo {
                            : (2 * RD * K * TPL <= 1024 ? 2 * RD : RD);
   static constexpr int LINES = RPB * K;
   static constexpr int THREADS = ((LINES * TPL + 63) / 64) * 64;
+  // LDS: the padded twiddle table, then LINES padded lines, then (FP64 only)
+  // LINES more holding the rows of Z as read (the pointwise terms take Z
+  // from there instead of reading global memory a second time)
+  static constexpr int LSTR = padded_len(N);
+  template <typename T> static constexpr bool stash() {
+    return sizeof(T) == 8 && 2 * sizeof(T) * ((size_t)LSTR + 2 * (size_t)LINES * LSTR) <= 150 * 1024;
+  }
+  template <typename T> static constexpr size_t lds_elems() {
+    return (size_t)LSTR + (size_t)LINES * LSTR * (stash<T>() ? 2 : 1);
+  }
 };
 
 template <typename T, int N, int F, int VAR>
@@ -356,18 +387,24 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
   using T2 = c_t<T>;
   constexpr int K = 2 * F + 1;
   constexpr int TPL = Geo<N>::TPL;
-  constexpr int RPB = XGeo<N, K, VAR>::RPB;
-  constexpr int LINES = XGeo<N, K, VAR>::LINES;
+  using G = XGeo<N, K, VAR>;
+  constexpr int RPB = G::RPB;
+  constexpr int LINES = G::LINES;
+  constexpr int LSTR = G::LSTR;
+  constexpr bool kStash = G::template stash<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* tw = reinterpret_cast<T2*>(smem_raw);
-  T2* lds = tw + N;
+  T2* lds = tw + LSTR;
+  T2* zraw = kStash ? lds + LINES * LSTR : nullptr;
   const int t = threadIdx.x;
-  for (int m = t; m < N; m += blockDim.x) tw[m] = twg[m];
+  for (int m = t; m < N; m += blockDim.x) tw[pad8(m)] = twg[m];
   const long row0 = blk * RPB;
 
   // ---- c64: prefetch the pointwise operands of this thread's first point so
-  // their latency hides behind the transforms below (in FP64 the extra live
-  // registers would cost more occupancy than the overlap gains)
+  // their latency hides behind the transforms below.  FP64 instead keeps the
+  // rows of Z in LDS as the first transform pass reads them (an FP64 row
+  // block's traffic evicts Z from L2 before the pointwise loop would re-read
+  // it), and loads X, L X and V in the pointwise loop.
   constexpr bool kPrefetch = sizeof(T) == 4;
   int pt = t;
   bool have = pt < RPB * N && row0 + pt / N < nrows;
@@ -378,7 +415,8 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       x[i] = X[i * npts + j];
-      z[i] = Z[i * npts + j];
+      if constexpr (kStash) z[i] = zraw[(i * RPB + pt / N) * LSTR + pad8(pt % N)];
+      else z[i] = Z[i * npts + j];
       y[i] = Y[i * npts + j];
     }
     vj = V[j];
@@ -393,13 +431,13 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
   lc.valid = ls < LINES && row0 + r < nrows;
   lc.goff = (size_t)comp * npts + (size_t)(row0 + r) * N;
   lc.gstride = 1;
-  lc.lbase = ls * (N + 1);
+  lc.lbase = ls * LSTR;
   lc.lstride = 1;
   const T invn = T(1) / T(N);
   double pars = 0.0;
   const Epi<T> none{nullptr, nullptr, T(0)};
-  fwd_stages<T, N, 0>(Z, lds, tw, lc, lamc, invn, pars);
-  inv_stages<T, N, 0, false>(lds, tw, nullptr, none, lc);
+  fwd_stages<T, N, 0, true>(Z, lds, tw, lc, lamc, invn, pars, zraw);
+  inv_stages<T, N, 0, false, true>(lds, tw, nullptr, none, lc);
 
   // ---- pointwise Hessian terms, W = L_x Z + q
   T zcoef[K];
@@ -421,7 +459,7 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
       s_zz += cabs2(z[i]);
     }
     hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) {
-      const T2 lz = lds[(i * RPB + rr) * (N + 1) + xx];
+      const T2 lz = lds[(i * RPB + rr) * LSTR + pad8(xx)];
       W[i * npts + j] = cadd(lz, qi);
       const T xq = cdotr(x[i], qi);
       s_xw += xq;

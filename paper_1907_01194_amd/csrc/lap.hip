@@ -90,7 +90,7 @@ static void launch_xpass(const LapAxis& ax, size_t npts, const void* X, const vo
   using G = XGeo<N, K, VAR>;
   const long nrows = (long)(npts / N);
   const int grid = (int)((nrows + G::RPB - 1) / G::RPB);
-  const size_t lds = sizeof(T2) * (size_t)(N + G::LINES * (N + 1));
+  const size_t lds = sizeof(T2) * G::template lds_elems<T>();
   const T2* tw = reinterpret_cast<const T2*>(sizeof(T) == 8 ? ax.tw64 : ax.tw32);
   if (lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&hvp_xpass_kernel<T, N, F, VAR>),
