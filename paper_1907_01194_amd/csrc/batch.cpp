@@ -224,7 +224,11 @@ gpe_status ex_norms(gpe_batch* b, std::vector<Item>& g) {
     case 7: s = run(NormsArgs<double, float, 7>{}); break;
   }
   GPE_TRY(s);
-  return fin_nblk(b, g, 3 * (2 * b->F + 1), POST_NONE, no_gram(g.size()));
+  // the slots of <u_i, xi_i> and ||xi_i||^2 only where some problem has a xi
+  // (a problem without one reads only its ||u_i||^2)
+  bool any_xi = false;
+  for (auto& it : g) any_xi = any_xi || it.r->b != nullptr;
+  return fin_nblk(b, g, (any_xi ? 3 : 1) * (2 * b->F + 1), POST_NONE, no_gram(g.size()));
 }
 
 gpe_status ex_scale(gpe_batch* b, std::vector<Item>& g) {
@@ -661,8 +665,9 @@ gpe_status solve_single(gpe_handle* h, void* X, const gpe_solve_opts* o, gpe_sol
   return c.status;
 }
 
-// Time the batched fused x pass per schedule variant on zero fields (three
-// distinct buffers per problem, as at handle creation) and keep the fastest.
+// Time the batched fused x pass per schedule variant on pseudo-random fields
+// (three distinct buffers per problem, as at handle creation) and keep the
+// fastest.
 static gpe_status tune_batch(gpe_batch* b) {
   if (b->hs.size() < 2) return GPE_OK;
   gpe_handle* h0 = b->hs[0];
@@ -670,7 +675,11 @@ static gpe_status tune_batch(gpe_batch* b) {
   const bool w32 = b->prec == GPE_MIXED;
   for (gpe_handle* h : b->hs) {
     void* bufs[3] = {w32 ? h->Xp32 : h->Xp, w32 ? h->LX32 : h->LX64, w32 ? h->T32 : h->T64};
-    for (void* p : bufs) GPE_HIP(h, hipMemsetAsync(p, 0, h->nel * (w32 ? 8 : 16), b->st));
+    unsigned seed = 1;
+    for (void* p : bufs) {
+      if (w32) GPE_HIP(h, launch_single(FillArgs<float>{p, h->nel, seed++}, elementwise_blocks(h->nel), b->st));
+      else GPE_HIP(h, launch_single(FillArgs<double>{p, h->nel, seed++}, elementwise_blocks(h->nel), b->st));
+    }
   }
   hipEvent_t e0, e1;
   GPE_HIP(h0, hipEventCreate(&e0));

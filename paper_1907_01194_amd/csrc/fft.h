@@ -160,15 +160,19 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
   constexpr int NB = (B + TPL - 1) / TPL;
   constexpr bool LAST_FWD = FWD && (s == P.S - 1);
   T2 v[NB][R];
+  // padded reads at j = b + r B: with B a multiple of 8, pad8(j) = pad8(b) + pad8(r B)
+  constexpr bool kReadSplit = PAD && B % 8 == 0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = lc.tl + i * TPL;
     if (lc.valid && (B % TPL == 0 || b < B)) {
+      const int pb = lc.lbase + pad8(b);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int j = b + r * B;
-        v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[lidx<PAD>(lc, j)];
-        if (SRC == SRC_GLOBAL && raw) raw[lidx<PAD>(lc, j)] = v[i][r];
+        const int li = kReadSplit ? pb + pad8(r * B) : lidx<PAD>(lc, j);
+        v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[li];
+        if (SRC == SRC_GLOBAL && raw) raw[li] = v[i][r];
       }
     }
   }
@@ -189,9 +193,14 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
       }
       Dft<R, FWD, T2>::run(v[i]);
       const int base = (b / Ns) * Ns * R + k;
+      // padded writes at base + r Ns: split as for the reads when Ns is a
+      // multiple of 8, or when Ns = 1 and base is (R = 8)
+      constexpr bool kWriteSplit = PAD && (Ns % 8 == 0 || (Ns == 1 && R == 8));
+      const int pbase = lc.lbase + pad8(base);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = base + r * Ns;
+        const int lw = kWriteSplit ? pbase + (Ns == 1 ? r : pad8(r * Ns)) : lidx<PAD>(lc, idx);
         T2 val = v[i][r];
         if (LAST_FWD) {
           const int p = idx < N / 2 ? idx : idx - N;
@@ -201,7 +210,7 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
           val = cscale(val, sc);
         }
         if (DST == DST_LDS) {
-          lds[lidx<PAD>(lc, idx)] = val;
+          lds[lw] = val;
         } else {
           const size_t g = lc.goff + (size_t)idx * lc.gstride;
           T2 o = epi.acc ? cadd(epi.acc[g], val) : val;
@@ -250,6 +259,53 @@ __device__ __forceinline__ void inv_stages(c_t<T>* lds, const c_t<T>* tw, c_t<T>
   }
 }
 
+// Projection coefficients of the HVP (Lemma 4.1 with the measured Gram
+// system): sums slots 0 and 1 of the x pass's partials (ab.n per slot,
+// ab.stride apart) in a fixed order over the workgroup, solves the 2x2 Gram
+// system with the set point's component norms ab.gram and returns the
+// coefficients in c[0..1] (every thread); res: also stored in ab.res[32..33].
+__device__ inline void ab_coeffs(const AbSrc& ab, int F, bool store, double* c) {
+  __shared__ double red2[2][1024 / kWave];
+  __shared__ double cf[2];
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = t; b < ab.n; b += blockDim.x) {
+    s0 += ab.part[b];
+    s1 += ab.part[ab.stride + b];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (t % kWave == 0) {
+    red2[0][t / kWave] = s0;
+    red2[1][t / kWave] = s1;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double w0 = 0.0, w1 = 0.0;
+    for (int w = 0; w < ((int)blockDim.x + kWave - 1) / kWave; ++w) {
+      w0 += red2[0][w];
+      w1 += red2[1][w];
+    }
+    double a11 = 0, a12 = 0, a22 = 0;
+    for (int q = 0; q < 2 * F + 1; ++q) {
+      const double l = F - q;
+      a11 += ab.gram[q];
+      a12 += l * ab.gram[q];
+      a22 += l * l * ab.gram[q];
+    }
+    const double det = a11 * a22 - a12 * a12;
+    cf[0] = (a22 * w0 - a12 * w1) / det;
+    cf[1] = (a11 * w1 - a12 * w0) / det;
+    if (store) {
+      ab.res[32] = cf[0];
+      ab.res[33] = cf[1];
+    }
+  }
+  __syncthreads();
+  c[0] = cf[0];
+  c[1] = cf[1];
+}
+
 // One axis pass for every line of every component: out = acc + L_a(in)
 // [- (coef[0] + coef[1] l) X], with the Parseval sum <in, L_a in> per workgroup
 // in part[slot * stride + wg] when part != null.
@@ -295,42 +351,8 @@ __device__ __forceinline__ void lap_body(const c_t<T>* __restrict__ in, const c_
   Epi<T> epi{acc, nullptr, T(0)};
   double c0 = 0.0, c1 = 0.0;
   if (X && ab.part) {   // uniform: the coefficients from the x pass's partials
-    __shared__ double red2[2][1024 / kWave];
-    __shared__ double cf[2];
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = t; b < ab.n; b += blockDim.x) {
-      s0 += ab.part[b];
-      s1 += ab.part[ab.stride + b];
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if (t % kWave == 0) {
-      red2[0][t / kWave] = s0;
-      red2[1][t / kWave] = s1;
-    }
-    __syncthreads();
-    if (t == 0) {
-      double w0 = 0.0, w1 = 0.0;
-      for (int w = 0; w < ((int)blockDim.x + kWave - 1) / kWave; ++w) {
-        w0 += red2[0][w];
-        w1 += red2[1][w];
-      }
-      double a11 = 0, a12 = 0, a22 = 0;
-      for (int q = 0; q < 2 * F + 1; ++q) {
-        const double l = F - q;
-        a11 += ab.gram[q];
-        a12 += l * ab.gram[q];
-        a22 += l * l * ab.gram[q];
-      }
-      const double det = a11 * a22 - a12 * a12;
-      cf[0] = (a22 * w0 - a12 * w1) / det;
-      cf[1] = (a11 * w1 - a12 * w0) / det;
-      if (blk == 0) {
-        ab.res[32] = cf[0];
-        ab.res[33] = cf[1];
-      }
-    }
-    __syncthreads();
+    double cf[2];
+    ab_coeffs(ab, F, blk == 0, cf);
     c0 = cf[0];
     c1 = cf[1];
   } else if (X) {
@@ -400,28 +422,33 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
   for (int m = t; m < N; m += blockDim.x) tw[pad8(m)] = twg[m];
   const long row0 = blk * RPB;
 
-  // ---- c64: prefetch the pointwise operands of this thread's first point so
-  // their latency hides behind the transforms below.  FP64 instead keeps the
-  // rows of Z in LDS as the first transform pass reads them (an FP64 row
-  // block's traffic evicts Z from L2 before the pointwise loop would re-read
-  // it), and loads X, L X and V in the pointwise loop.
-  constexpr bool kPrefetch = sizeof(T) == 4;
+  // ---- prefetch the global pointwise operands of this thread's first point
+  // (X, L X, V, and Z where it is not kept in LDS) so that their latency
+  // hides behind the transforms below.  FP64 keeps the rows of Z in LDS as
+  // the first transform pass reads them (an FP64 row block's traffic evicts Z
+  // from L2 before the pointwise loop would re-read it); they are taken from
+  // there once the transforms are done.
   int pt = t;
   bool have = pt < RPB * N && row0 + pt / N < nrows;
   T2 x[K], z[K], y[K];
   T vj = T(0);
   size_t j = have ? (size_t)(row0 + pt / N) * N + pt % N : 0;
-  auto load_point = [&]() {
+  auto load_global = [&]() {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       x[i] = X[i * npts + j];
-      if constexpr (kStash) z[i] = zraw[(i * RPB + pt / N) * LSTR + pad8(pt % N)];
-      else z[i] = Z[i * npts + j];
+      if constexpr (!kStash) z[i] = Z[i * npts + j];
       y[i] = Y[i * npts + j];
     }
     vj = V[j];
   };
-  if (kPrefetch && have) load_point();
+  auto load_stashed = [&]() {
+    if constexpr (kStash) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) z[i] = zraw[(i * RPB + pt / N) * LSTR + pad8(pt % N)];
+    }
+  };
+  if (have) load_global();
 
   // ---- L_x Z for the RPB rows of every component, left in LDS
   LineCtx lc;
@@ -473,22 +500,14 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
     acc[4] += (double)s_zq;
     acc[5] += (double)s_zz;
   };
-  if constexpr (kPrefetch) {
-    while (have) {
-      point(pt / N, pt % N);
-      pt += blockDim.x;
-      have = pt < RPB * N && row0 + pt / N < nrows;
-      if (have) {
-        j = (size_t)(row0 + pt / N) * N + pt % N;
-        load_point();
-      }
-    }
-  } else {
-    for (pt = t; pt < RPB * N; pt += blockDim.x) {
-      if (row0 + pt / N >= nrows) break;
+  while (have) {
+    load_stashed();
+    point(pt / N, pt % N);
+    pt += blockDim.x;
+    have = pt < RPB * N && row0 + pt / N < nrows;
+    if (have) {
       j = (size_t)(row0 + pt / N) * N + pt % N;
-      load_point();
-      point(pt / N, pt % N);
+      load_global();
     }
   }
   block_partials_any<7>(acc, part, stride, blk);

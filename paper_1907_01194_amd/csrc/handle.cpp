@@ -170,9 +170,12 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
          hvp_xpass<T>(h->F, h->ax[0], h->npts, Xw, Z, Yw, Vw, HZ, p, h->part, h->pstride, &nbx, h->xvar, skip, h->st));
   for (int q = 0; q < 7; ++q) nb.nb[q] = nbx;
   double* coef = h->res + 32;
-  // few x-pass workgroups: the last axis pass forms the projection coefficients itself
+  // Projection coefficients (Lemma 4.1) from the x pass's partials: with few
+  // x-pass workgroups every workgroup of the last axis pass forms them itself;
+  // in 3D otherwise one extra workgroup of the y pass does; else a finalize.
   const bool ab_local = riem && h->dim >= 2 && nbx <= kAbLocalMax;
-  if (riem && !ab_local)
+  const bool ab_ypass = riem && !ab_local && h->dim == 3;
+  if (riem && !ab_local && !ab_ypass)
     GPE_KT(h, KK_FINALIZE,
            finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, skip, h->st));
   int nq = 7;
@@ -184,11 +187,13 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   } else {
     for (int a = 1; a < h->dim; ++a) {
       const bool proj = riem && a == h->dim - 1;
-      AbSrc ab;
+      AbSrc ab, fin;
       if (proj && ab_local) ab = AbSrc{h->part, h->pstride, nbx, h->gram_pt, h->res};
+      if (a == 1 && ab_ypass) fin = AbSrc{h->part, h->pstride, nbx, h->gram_pt, h->res};
       GPE_KT(h, KK_LAP_X + a,
              lap_axis_ex<T>(h->ax[a], Z, HZ, HZ, h->F, h->npts, proj ? Xw : nullptr, coef, h->part, h->pstride,
-                            6 + a, &nb.nb[6 + a], skip, a == 1, ab.part ? &ab : nullptr, h->st));
+                            6 + a, &nb.nb[6 + a], skip, a == 1, ab.part ? &ab : nullptr, fin.part ? &fin : nullptr,
+                            h->st));
       nq = 7 + a;
     }
   }
@@ -199,18 +204,22 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
 }
 
 // Pick the fused x pass's rows-per-workgroup by timing each variant on the
-// handle's own grid (zero fields; the cost does not depend on the values).
+// handle's own grid.  The fields hold pseudo-random values rather than zeros:
+// the cost does not depend on the values, but the power drawn (and so the
+// clock the chip sustains) does.
 template <typename T>
 static gpe_status tune_xpass_t(gpe_handle* h) {
   const int nv = xpass_variants(h->n[0]);
   if (nv <= 1 || h->npts < (1u << 15)) return GPE_OK;
-  // three distinct zero fields for X, Z, LX (aliasing them would hide memory traffic)
+  // three distinct fields for X, Z, LX (aliasing them would hide memory traffic)
   void* A = sizeof(T) == 8 ? h->T64 : h->T32;
   void* Bz = sizeof(T) == 8 ? h->Xp : h->Xp32;
   void* C = sizeof(T) == 8 ? h->LX64 : h->LX32;
   void* Wt = h->Gp;                                // scratch output (c128, large enough)
   const T* Vw = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)h->V64 : (const void*)h->V32);
-  for (void* b : {A, Bz, C}) GPE_HIP(h, hipMemsetAsync(b, 0, h->nel * sizeof(T) * 2, h->st));
+  unsigned seed = 1;
+  for (void* b : {A, Bz, C})
+    GPE_HIP(h, launch_single(FillArgs<T>{b, h->nel, seed++}, elementwise_blocks(h->nel), h->st));
   hipEvent_t e0, e1;
   GPE_HIP(h, hipEventCreate(&e0));
   GPE_HIP(h, hipEventCreate(&e1));
@@ -280,12 +289,13 @@ gpe_status norms_enq(gpe_handle* h, const void* u, const void* xi, bool xi32) {
     GPE_KT(h, KK_NORMS, (comp_norms<double, float>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
   else
     GPE_KT(h, KK_NORMS, (comp_norms<double, double>(h->K, u, xi, h->part, h->nblk, h->npts, h->st)));
-  return finalize_enq(h, 3 * h->K, POST_NONE, nullptr);
+  // without xi only the K slots of ||u_i||^2 are written, so only they are summed
+  return finalize_enq(h, xi ? 3 * h->K : h->K, POST_NONE, nullptr);
 }
 
 gpe_status norms_read(gpe_handle* h, bool has_xi, RetractNorms* rn) {
   const int K = h->K;
-  GPE_TRY(finite(h, h->hres, 3 * K, "the component norms"));
+  GPE_TRY(finite(h, h->hres, has_xi ? 3 * K : K, "the component norms"));
   for (int i = 0; i < K; ++i) {
     rn->uu[i] = h->hres[i];
     rn->ux[i] = has_xi ? h->hres[K + i] : 0.0;
@@ -490,6 +500,21 @@ using namespace gpe;
 // ----------------------------------------------------------------- C ABI
 
 
+// Validation of a problem statement (gpe_problem's contract); "" if valid.
+static std::string problem_error(const gpe_problem* pr) {
+  if (pr->F < 1 || pr->F > 3) return "F must be 1, 2 or 3";
+  if (pr->dim < 1 || pr->dim > 3) return "dim must be 1, 2 or 3";
+  if (!(std::fabs(pr->M) < pr->F)) return "|M| must be < F";
+  if (pr->M < 0) return "M < 0: reverse the component order and pass -M";
+  for (int a = 0; a < pr->dim; ++a) {
+    const int n = pr->n[a];
+    if (!lap_size_supported(n))
+      return "n[" + std::to_string(a) + "] = " + std::to_string(n) + " unsupported (2^k or 3*2^k, 4..512)";
+    if (!(pr->hi[a] > pr->lo[a])) return "empty box";
+  }
+  return "";
+}
+
 extern "C" {
 
 const char* gpe_version(void) { return "gpe 0.1 (gfx950)"; }
@@ -561,17 +586,10 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V, int precision, voi
   if (!out) return fail(nullptr, GPE_EINVAL, "out is NULL");
   *out = nullptr;
   if (!pr || !V) return fail(nullptr, GPE_EINVAL, "problem or potential is NULL");
-  if (pr->F < 1 || pr->F > 3) return fail(nullptr, GPE_EINVAL, "F must be 1, 2 or 3");
-  if (pr->dim < 1 || pr->dim > 3) return fail(nullptr, GPE_EINVAL, "dim must be 1, 2 or 3");
   if (precision != GPE_FP64 && precision != GPE_MIXED) return fail(nullptr, GPE_EINVAL, "bad precision");
-  if (!(std::fabs(pr->M) < pr->F)) return fail(nullptr, GPE_EINVAL, "|M| must be < F");
-  if (pr->M < 0) return fail(nullptr, GPE_EINVAL, "M < 0: reverse the component order and pass -M");
-  for (int a = 0; a < pr->dim; ++a) {
-    const int n = pr->n[a];
-    if (!lap_size_supported(n))
-      return fail(nullptr, GPE_EINVAL, "n[" + std::to_string(a) + "] = " + std::to_string(n) +
-                                           " unsupported (2^k or 3*2^k, 4..512)");
-    if (!(pr->hi[a] > pr->lo[a])) return fail(nullptr, GPE_EINVAL, "empty box");
+  {
+    const std::string err = problem_error(pr);
+    if (!err.empty()) return fail(nullptr, GPE_EINVAL, err);
   }
   gpe_handle* h = new gpe_handle();
   h->prob = *pr;

@@ -78,11 +78,14 @@ hipError_t hvp_xpass(int F, const LapAxis& ax, size_t npts, const void* X, const
 int xpass_variants(int n);
 
 // Axis pass with Parseval partial <Z, L_a Z> into part[slot * stride + wg] and,
-// if coef != null, the projection epilogue out -= (coef[0] + coef[1] l) X.
+// if coef != null, the projection epilogue out -= (coef[0] + coef[1] l) X
+// (coefficients from coef, or formed in the pass from ab).  fin non-null: one
+// more workgroup forms the projection coefficients from fin's partials into
+// fin->res[32..33] for a later pass of the same HVP.
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nblk_out,
-                       const double* skip, int rev, const AbSrc* ab, hipStream_t st);
+                       const double* skip, int rev, const AbSrc* ab, const AbSrc* fin, hipStream_t st);
 size_t lap_max_blocks(const LapAxis& ax, int K);
 
 // Post-processing done by the single-block finalize kernel after summing the
@@ -243,6 +246,11 @@ template <typename TA, typename TB, typename TO> struct DiffArgs {   // out = a 
   const void* b;
   void* out;
   size_t n;
+};
+template <typename T> struct FillArgs {   // out = pseudo-random complex values in [-1, 1) (timing data)
+  void* out;
+  size_t n;
+  unsigned seed;
 };
 template <typename TI, typename TO> struct ConvArgs {   // dst = src (converted); src null: dst = 0
   const void* src;

@@ -15,13 +15,28 @@
 
 namespace gpe {
 
+// fin.part non-null: the launch has one more workgroup, dispatched first,
+// that forms the HVP's projection coefficients from the x pass's partials
+// into fin.res[32..33] for a later pass (instead of a finalize launch).
 template <typename T, int N>
 __global__ void __launch_bounds__(Geo<N>::THREADS)
 lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
                 const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F, size_t npts,
                 const c_t<T>* __restrict__ X, const double* __restrict__ coef, double* __restrict__ part,
-                size_t stride, int slot, const double* skip, int rev, AbSrc ab) {
-  const long blk = rev ? (long)gridDim.x - 1 - (long)blockIdx.x : (long)blockIdx.x;
+                size_t stride, int slot, const double* skip, int rev, AbSrc ab, AbSrc fin) {
+  long b = (long)blockIdx.x;
+  long nb = (long)gridDim.x;
+  if (fin.part) {
+    if (b == 0) {
+      if (skip && *skip != 0.0) return;
+      double cf[2];
+      ab_coeffs(fin, F, true, cf);
+      return;
+    }
+    --b;
+    --nb;
+  }
+  const long blk = rev ? nb - 1 - b : b;
   lap_body<T, N>(in, acc, out, twg, nlines, inner, lamc, F, npts, X, coef, part, stride, slot, blk, skip, ab);
 }
 
@@ -36,18 +51,19 @@ hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, con
 template <typename T, int N>
 static void launch_lap(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       const double* skip, int rev, const AbSrc* ab, hipStream_t st) {
+                       const double* skip, int rev, const AbSrc* ab, const AbSrc* fin, hipStream_t st) {
   using T2 = c_t<T>;
   constexpr int LPB = Geo<N>::LPB;
   const long nlines = ax.nlines;
   const int grid = (int)((nlines + LPB - 1) / LPB);
   const size_t lds = sizeof(T2) * (size_t)(N + LPB * (N + 1));
   const T2* tw = reinterpret_cast<const T2*>(sizeof(T) == 8 ? ax.tw64 : ax.tw32);
-  hipLaunchKernelGGL((lap_axis_kernel<T, N>), dim3(grid), dim3(Geo<N>::THREADS), lds, st,
+  hipLaunchKernelGGL((lap_axis_kernel<T, N>), dim3(grid + (fin ? 1 : 0)), dim3(Geo<N>::THREADS), lds, st,
                      reinterpret_cast<const T2*>(in), reinterpret_cast<const T2*>(acc),
                      reinterpret_cast<T2*>(out), tw, nlines, ax.inner, (T)ax.lamc, F, npts,
-                     reinterpret_cast<const T2*>(X), coef, part, stride, slot, skip, rev, ab ? *ab : AbSrc{});
-  if (nb) *nb = grid;
+                     reinterpret_cast<const T2*>(X), coef, part, stride, slot, skip, rev, ab ? *ab : AbSrc{},
+                     fin ? *fin : AbSrc{});
+  if (nb) *nb = grid;   // partials of the pass itself (the extra workgroup writes none)
 }
 
 #define GPE_SIZES(M) M(4) M(6) M(8) M(12) M(16) M(24) M(32) M(48) M(64) M(96) M(128) M(192) M(256) M(384) M(512)
@@ -57,7 +73,8 @@ hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* ou
   switch (ax.n) {
 #define GPE_CASE(NN) \
   case NN:                                                                                                       \
-    launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, nullptr, st); \
+    launch_lap<T, NN>(ax, in, acc, out, 0, 1, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, nullptr,     \
+                      nullptr, st);                                                                               \
     break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
@@ -69,10 +86,10 @@ hipError_t lap_axis(const LapAxis& ax, const void* in, const void* acc, void* ou
 template <typename T>
 hipError_t lap_axis_ex(const LapAxis& ax, const void* in, const void* acc, void* out, int F, size_t npts,
                        const void* X, const double* coef, double* part, size_t stride, int slot, int* nb,
-                       const double* skip, int rev, const AbSrc* ab, hipStream_t st) {
+                       const double* skip, int rev, const AbSrc* ab, const AbSrc* fin, hipStream_t st) {
   switch (ax.n) {
-#define GPE_CASE(NN)                                                                                     \
-  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, skip, rev, ab, st); \
+#define GPE_CASE(NN)                                                                                          \
+  case NN: launch_lap<T, NN>(ax, in, acc, out, F, npts, X, coef, part, stride, slot, nb, skip, rev, ab, fin, st); \
     break;
     GPE_SIZES(GPE_CASE)
 #undef GPE_CASE
@@ -165,10 +182,10 @@ template hipError_t lap_axis<double>(const LapAxis&, const void*, const void*, v
 template hipError_t lap_axis<float>(const LapAxis&, const void*, const void*, void*, hipStream_t);
 template hipError_t lap_axis_ex<double>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
                                         const double*, double*, size_t, int, int*, const double*, int,
-                                        const AbSrc*, hipStream_t);
+                                        const AbSrc*, const AbSrc*, hipStream_t);
 template hipError_t lap_axis_ex<float>(const LapAxis&, const void*, const void*, void*, int, size_t, const void*,
                                        const double*, double*, size_t, int, int*, const double*, int,
-                                       const AbSrc*, hipStream_t);
+                                       const AbSrc*, const AbSrc*, hipStream_t);
 template hipError_t hvp_xpass<double>(int, const LapAxis&, size_t, const void*, const void*, const void*,
                                       const double*, void*, const PwParams&, double*, size_t, int*, int,
                                       const double*, hipStream_t);
