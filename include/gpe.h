@@ -210,6 +210,24 @@ gpe_status gpe_hvp_dot(gpe_handle* h, const void* Z, void* HZ, double sigma, dou
 gpe_status gpe_retract(gpe_handle* h, const void* X, const void* Xi, double t, int kind,
                        void* Xout);
 
+/* Retraction with no allocation, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc): gpe_retract
+ * without a handle, for the problem *prob (validated as gpe_create does).
+ * Xout = psi(X + t Xi) by retraction `kind` (Xi may be NULL: psi(X)); X, Xi,
+ * Xout: device c128 fields of that problem on the current device; Xout may
+ * alias X.  Work is ordered on `stream` (hipStream_t, NULL = default) and
+ * the call synchronises it (the scalar solve runs on the host).  The same
+ * kernels as gpe_retract run, so the results are identical.
+ * Scratch: a static device array of the library (about 345 KB per GPU, kept
+ * until the process ends) holds the FP64 partial sums; it fits every problem
+ * gpe_problem admits (a larger partial count is rejected with GPE_EINVAL).
+ * The array is shared by all calls on one GPU, so calls on one GPU must not
+ * overlap (from several host threads or streams): overlapping calls race.
+ * Errors: as gpe_retract, plus GPE_EINVAL for an invalid problem; message in
+ * gpe_last_error(NULL). */
+gpe_status gpe_retract_noalloc(const gpe_problem* prob, const void* X, const void* Xi, double t, int kind,
+                               void* Xout, void* stream);
+
 /* Orthogonal projection onto the tangent space at X (Lemma 4.1, solved with
  * the measured Gram matrix of u and Gamma u): out = W - alpha X - beta Gamma X.
  * X, W, out: device c128 fields; out may alias W.  Synchronises. */

@@ -76,6 +76,8 @@ SIGNATURES = {
     "gpe_hvp_dot": (c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(c_double)]),
     "gpe_retract": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_void_p]),
     "gpe_constraints": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    "gpe_retract_noalloc": (c_int, [ctypes.POINTER(gpe_problem), c_void_p, c_void_p, c_double, c_int, c_void_p,
+                                    c_void_p]),
     "gpe_newton_solve": (c_int, [c_void_p, c_void_p, ctypes.POINTER(gpe_solve_opts),
                                  ctypes.POINTER(gpe_solve_stats)]),
     "gpe_project": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -163,6 +165,23 @@ def problem_struct(spec):
         pr.beta[k] = float(beta[k])
     pr.p, pr.q, pr.M = float(spec.p), float(spec.q), float(spec.M)
     return pr
+
+
+def retract_noalloc(spec, X, Xi, t=1.0, kind=R1, out=None):
+    """gpe_retract_noalloc: Xout = psi(X + t Xi) with no handle and no device
+    allocation by the library (X, Xi, out: complex128 CUDA tensors of the
+    problem's field shape; Xi may be None).  Runs on torch's current stream."""
+    import torch
+    shape = (2 * int(spec.F) + 1,) + tuple(reversed(tuple(spec.n)))
+    Xo = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=X.device)
+    pr = problem_struct(spec)
+    xi = _ptr(Xi, torch.complex128, shape) if Xi is not None else None
+    st = lib().gpe_retract_noalloc(ctypes.byref(pr), _ptr(X, torch.complex128, shape), xi, float(t), int(kind),
+                                   _ptr(Xo, torch.complex128, shape),
+                                   c_void_p(torch.cuda.current_stream(X.device).cuda_stream))
+    if st != 0:
+        raise GpeError(st, lib().gpe_last_error(None).decode())
+    return Xo
 
 
 def potential(spec, grid_shape):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -515,6 +516,38 @@ static std::string problem_error(const gpe_problem* pr) {
   return "";
 }
 
+// ----------------------------------------------------------------- scratch of gpe_retract_noalloc
+// The retraction's partial sums (3K slots of at most kMaxRedBlocks workgroups),
+// the finalize's results and its ticket, for every admissible problem.  One
+// copy per GPU, at a device address found once per device.
+namespace {
+constexpr size_t kNaPart = 3 * 7 * (size_t)kMaxRedBlocks;
+constexpr size_t kNaRes = 64;
+constexpr size_t kNaDoubles = kNaPart + kNaRes + 2;   // + the ticket (first 4 bytes of the last 16)
+constexpr int kNaMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[kNaDoubles];
+static double* g_scratch_ptr[kNaMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (resolved once per device).
+static gpe_status scratch_on_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kNaMaxDevices) return fail(nullptr, GPE_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(nullptr, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GPE_OK;
+}
+
 extern "C" {
 
 const char* gpe_version(void) { return "gpe 0.1 (gfx950)"; }
@@ -891,6 +924,60 @@ gpe_status gpe_timing_read(gpe_handle* h, int max, const char** names, int* coun
     ++k;
   }
   if (nkinds) *nkinds = k;
+  return GPE_OK;
+}
+
+gpe_status gpe_retract_noalloc(const gpe_problem* pr, const void* X, const void* Xi, double t, int kind, void* Xout,
+                               void* stream) {
+  if (!pr || !X || !Xout) return fail(nullptr, GPE_EINVAL, "NULL argument");
+  {
+    const std::string err = problem_error(pr);
+    if (!err.empty()) return fail(nullptr, GPE_EINVAL, err);
+  }
+  if (kind != GPE_R1_PROJECTIVE && kind != GPE_R2_ORTHOGONAL && kind != GPE_R3_CLOSED)
+    return fail(nullptr, GPE_EINVAL, "unknown retraction kind");
+  const int F = pr->F, K = 2 * F + 1;
+  size_t npts = 1;
+  for (int a = 0; a < pr->dim; ++a) npts *= (size_t)pr->n[a];
+  const int nblk = red_blocks(npts);
+  const int nq = Xi ? 3 * K : K;   // without Xi the norms kernel writes the K slots of ||X_i||^2 only
+  if ((size_t)3 * K * (size_t)nblk > kNaPart) return fail(nullptr, GPE_EINVAL, "problem exceeds the static scratch");
+  double* base = nullptr;
+  GPE_TRY(scratch_on_device(&base));
+  double* part = base;
+  double* res = base + kNaPart;
+  unsigned int* ticket = reinterpret_cast<unsigned int*>(base + kNaPart + kNaRes);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+#define NA_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) return hip_fail(nullptr, e_, #call);        \
+  } while (0)
+  // the ticket starts at 0 (a finalize leaves it there; an interrupted call might not)
+  NA_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned int), st));
+  NA_HIP((comp_norms<double, double>(K, X, Xi, part, nblk, npts, st)));
+  SlotCounts nb;
+  for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = nblk;
+  NA_HIP(finalize(part, nblk, nb, nq, res, POST_NONE, F, nullptr, ticket, nullptr, st));
+  double r[3 * 7];
+  NA_HIP(hipMemcpyAsync(r, res, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
+  NA_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < nq; ++i)
+    if (!std::isfinite(r[i])) return fail(nullptr, GPE_ENUMERIC, "NaN or Inf in the component norms");
+  double a[7], sig[7];
+  for (int i = 0; i < K; ++i) {
+    const double ux = Xi ? r[K + i] : 0.0, xx = Xi ? r[2 * K + i] : 0.0;
+    a[i] = r[i] + 2.0 * t * ux + t * t * xx;   // ||u_i + t xi_i||^2
+    if (a[i] < 0) a[i] = 0;
+  }
+  const int rs = kind == GPE_R1_PROJECTIVE ? sigma_projective(F, pr->M, a, sig)
+               : kind == GPE_R2_ORTHOGONAL ? sigma_orthogonal(F, pr->M, a, sig)
+                                           : sigma_closed(F, pr->M, a, sig);
+  if (rs != SIGMA_OK)
+    return fail(nullptr, GPE_EDOMAIN, kind == GPE_R3_CLOSED ? "retraction argument outside S"
+                                                            : "retraction argument outside Omega");
+  NA_HIP((scale_comps<double, double, double>(K, X, Xi, t, sig, Xout, npts, st)));
+#undef NA_HIP
   return GPE_OK;
 }
 
