@@ -43,9 +43,55 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes), by precision and
 # schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": None,
-    "traffic": {},      # {prec: {variant: {kernel kind: bytes per launch}}}
-    "valu": {},         # {prec: {variant: VALU instructions per x-pass launch}}
+    "src_hash": "665e4ccdd92b8ea9",
+    "traffic": {
+        "fp64": {
+            "0": {
+                "hvp_xpass": 960318901,
+                "lap_axis_y": 705329686,
+                "lap_axis_z": 939957037
+            },
+            "1": {
+                "hvp_xpass": 958502622,
+                "lap_axis_y": 705329686,
+                "lap_axis_z": 939957037
+            },
+            "2": {
+                "hvp_xpass": 957680453,
+                "lap_axis_y": 705329686,
+                "lap_axis_z": 939957037
+            }
+        },
+        "mixed": {
+            "0": {
+                "hvp_xpass": 482111799,
+                "lap_axis_y": 352855956,
+                "lap_axis_z": 470162608
+            },
+            "1": {
+                "hvp_xpass": 481762173,
+                "lap_axis_y": 352855956,
+                "lap_axis_z": 470162608
+            },
+            "2": {
+                "hvp_xpass": 479390402,
+                "lap_axis_y": 352855956,
+                "lap_axis_z": 470162608
+            }
+        }
+    },
+    "valu": {
+        "fp64": {
+            "0": 67518464,
+            "1": 67493888,
+            "2": 64040960
+        },
+        "mixed": {
+            "0": 66830336,
+            "1": 66527232,
+            "2": 63459328
+        }
+    }
 }
 
 
