@@ -130,6 +130,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--paper-tables", action="store_true",
                     help="only reproduce the ARNT rows of the Sec. 7.1 tables (every magnetization, R1/R2/R3)")
+    ap.add_argument("--tables", default="", help="with --paper-tables: comma list of tables (default: all)")
+    ap.add_argument("--table-cap", type=float, default=120.0, help="with --paper-tables: seconds per solve")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the paper's spin-3 128^3 ground-state solve (for profiling the whole solve)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -407,7 +409,7 @@ def batch_measure(count, steps, solve, sequential, log):
     return out
 
 
-def paper_tables(log):
+def paper_tables(log, tables=None, cap=120.0):
     """ARNT on the Sec. 7.1 workloads (Tables 1-1-2 .. 1-3-3): every printed
     magnetization with the three retractions, FP64, one mesh, ||grad|| <= 1e-6,
     the paper's initial data.  Energies against the printed ones; times are this
@@ -417,6 +419,8 @@ def paper_tables(log):
     from paper_1907_01194_amd.binding import Problem
     rows = []
     for table, t in W.PAPER_TABLES.items():
+        if tables and table not in tables:
+            continue
         for M, E_paper in t["E"].items():
             spec, X0 = W.paper_table_case(table, M)
             for retr in (1, 2, 3):
@@ -424,7 +428,7 @@ def paper_tables(log):
                 X = torch.from_numpy(X0).cuda()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, st = gp.newton_solve(X, check=False, tol=1e-6, retraction=retr, time_limit=120.0)
+                _, st = gp.newton_solve(X, check=False, tol=1e-6, retraction=retr, time_limit=cap)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 gp.close()
@@ -564,8 +568,9 @@ def main():
         copy_calibration(log)
         return
     if args.paper_tables:
-        rows = paper_tables(log)
-        print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6}), flush=True)
+        rows = paper_tables(log, [t for t in args.tables.split(",") if t], args.table_cap)
+        print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6, "cap_s": args.table_cap}),
+              flush=True)
         return
     from paper_1907_01194_amd import workloads as W
     from paper_1907_01194_amd.binding import TRACE_NAMES
