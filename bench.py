@@ -21,7 +21,7 @@ batched HVP pass against the same HVPs one by one, and the lock-step Newton
 solve against one-by-one solves) and the CPU oracle's timings.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-solve] [--no-cpu]
-                    [--no-batch] [--no-batch-sequential]
+                    [--no-batch] [--no-batch-solve] [--no-batch-sequential] [--batch-only]
 """
 
 import argparse
@@ -96,14 +96,22 @@ MEASURED = {
 
 
 def kernel_src_hash():
-    """Hash of every device source and header of the library."""
+    """Hash of the sources of the kernels an HVP launches (the x, y and z passes):
+    lap.hip and every library header it includes, directly or not."""
     import hashlib
-    h = hashlib.sha256()
+    import re
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1907_01194_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    todo, seen = ["lap.hip"], []
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(d, f)):
+            continue
+        seen.append(f)
+        todo += re.findall(r'#include "([^"]+)"', open(os.path.join(d, f)).read())
+    h = hashlib.sha256()
+    for f in sorted(seen):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -134,6 +142,8 @@ def parse():
     ap.add_argument("--table-cap", type=float, default=120.0, help="with --paper-tables: seconds per solve")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the paper's spin-3 128^3 ground-state solve (for profiling the whole solve)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched measurements (for profiling the batched kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (reference for HBM counters)")
     return ap.parse_args()
@@ -342,37 +352,44 @@ def batch_measure(count, steps, solve, sequential, log):
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    for _ in range(5):
-        b.hvp(Z, True, sig, HZ)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
-        b.hvp(Z, True, sig, HZ)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batched_ms = e0.elapsed_time(e1) / steps
-    for p, z, h in zip(b.problems, Z, HZ):
-        p.hvp_dot(z, 1e-2, out=h)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def seq(dot):
         for p, z, h in zip(b.problems, Z, HZ):
-            p.hvp_dot(z, 1e-2, out=h)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    seq_ms = e0.elapsed_time(e1) / steps
+            if dot:
+                p.hvp_dot(z, 1e-2, out=h)
+            else:
+                p.hvp(z, True, 1e-2, out=h)
+
+    # back to back without kappa (no read-back), and with each pass's kappas on the host
+    batched_ms = timed(lambda: b.hvp(Z, True, sig, HZ, kappa=False))
+    batched_k_ms = timed(lambda: b.hvp(Z, True, sig, HZ))
+    seq_ms = timed(lambda: seq(False))
+    seq_k_ms = timed(lambda: seq(True))
     pts = sum(int(np.prod(sp.n)) for sp in specs)
     sizes = {}
     for sp in specs:
         sizes[sp.n[0]] = sizes.get(sp.n[0], 0) + 1
-    log("batch of %d (%s): %.1f us per batched HVP pass, %.1f us one by one; x-pass variant %d %s" % (
-        count, sizes, 1e3 * batched_ms, 1e3 * seq_ms, sched[0], sched[1]))
+    log("batch of %d (%s): %.1f us per batched HVP pass (%.1f with kappa read-back), %.1f us one by one "
+        "(%.1f); x-pass variant %d %s" % (count, sizes, 1e3 * batched_ms, 1e3 * batched_k_ms, 1e3 * seq_ms,
+                                           1e3 * seq_k_ms, sched[0], sched[1]))
     out = {"workload": "%d spin-1 2D problems, n^2 with n in {64,128,256}, [-12,12]^2, lattice V, "
                        "beta=(100, U[-1,1]), M=U[0,0.9], seed 5" % count,
            "grid_counts": {str(k): v for k, v in sorted(sizes.items())}, "grid_points": pts,
            "precision": "mixed", "create_s": round(t_create, 3),
            "xpass_schedule": {"variant": sched[0], "us_per_variant": [round(x, 1) for x in sched[1]]},
            "batched_pass_us": round(1e3 * batched_ms, 2), "sequential_pass_us": round(1e3 * seq_ms, 2),
+           "batched_pass_kappa_readback_us": round(1e3 * batched_k_ms, 2),
+           "sequential_pass_kappa_readback_us": round(1e3 * seq_k_ms, 2),
            "hvp_per_s_batched": round(count / (batched_ms / 1e3), 1),
            "hvp_per_s_sequential": round(count / (seq_ms / 1e3), 1),
            "speedup": round(seq_ms / batched_ms, 2)}
@@ -571,6 +588,10 @@ def main():
         rows = paper_tables(log, [t for t in args.tables.split(",") if t], args.table_cap)
         print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6, "cap_s": args.table_cap}),
               flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": batch_measure(args.batch_count, 50, not args.no_batch_solve,
+                                                   not args.no_batch_sequential, log)}), flush=True)
         return
     from paper_1907_01194_amd import workloads as W
     from paper_1907_01194_amd.binding import TRACE_NAMES

@@ -323,8 +323,10 @@ gpe_status gpe_batch_handle(gpe_batch* b, int i, gpe_handle** h);
 
 /* HVPs of every problem at its set point (gpe_set_point on its handle
  * first) in one batched pass: HZ[i] = Hess(Z[i]) as gpe_hvp with sigma[i]
- * (NULL: 0); Z, HZ in the work precision.  kappa (count values, or NULL)
- * receives <Z_i, HZ_i>.  Synchronises. */
+ * (NULL: 0); Z, HZ in the work precision.  kappa (count values, host)
+ * receives <Z_i, HZ_i> and the call synchronises; with kappa NULL no kappa
+ * is formed and the launches stay queued on the batch's stream (no
+ * synchronisation, like gpe_hvp). */
 gpe_status gpe_batch_hvp(gpe_batch* b, const void* const* Z, void* const* HZ, int riemannian, const double* sigma,
                          double* kappa);
 

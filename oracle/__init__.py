@@ -30,11 +30,13 @@ from .solver import SolveOpts, solve, rgbb, arnt, tcg
 PINS = {
     "laplacian": "naive DFT of the discrete Laplace formula; plane-wave eigenpairs",
     "energy/grad": "harmonic closed form (E = sum(gamma)/2); finite differences",
+    "zeeman term": "closed form on the manifold with beta = 0: E* = d/2 - p M + q M (q >= 0), "
+                   "d/2 - p M + q F^2 (q < 0), reached by the solver",
     "hvp": "finite differences; phase/spin-rotation/homogeneity identities; symmetry",
     "projection/rgrad/rhess": "tangency, idempotence, Lemma 4.1 closed form",
     "retractions": "constraints exact; R(0)=u; second order; R1 = brute-force nearest point; "
                    "spin-1 closed-form cases 1-3 (Sec. 6.1)",
-    "solver": "paper Table 3-1 / Table 4-1 printed ground-state energies (1D)",
+    "solver": "paper Table 3-1 / Table 4-1 printed ground-state energies (1D); Zeeman closed form",
     "multigrid transfer": "coarse nodes kept; exact on trigonometric polynomials; mass preserved",
 }
 

@@ -398,16 +398,17 @@ class Batch:
         except Exception:
             pass
 
-    def hvp(self, Zs, riemannian=False, sigma=None, outs=None):
-        """HZ_i = Hess(Z_i) for every problem at its set point; returns (HZs, kappas)."""
+    def hvp(self, Zs, riemannian=False, sigma=None, outs=None, kappa=True):
+        """HZ_i = Hess(Z_i) for every problem at its set point; returns (HZs, kappas).
+        kappa=False: no kappas (None) and no synchronisation."""
         m = len(self.problems)
         outs = outs if outs is not None else [p.empty(work=True) for p in self.problems]
         zp = (c_void_p * m)(*[p._w(Z).value for p, Z in zip(self.problems, Zs)])
         hp = (c_void_p * m)(*[p._w(H).value for p, H in zip(self.problems, outs)])
         sg = (c_double * m)(*([0.0] * m if sigma is None else [float(x) for x in sigma]))
-        kap = (c_double * m)()
+        kap = (c_double * m)() if kappa else None
         self._check(lib().gpe_batch_hvp(self.b, zp, hp, int(bool(riemannian)), sg, kap))
-        return outs, list(kap)
+        return outs, (list(kap) if kappa else None)
 
     def newton_solve(self, Xs, check=True, **opts):
         """Lock-step gpe_newton_solve of every problem; returns (Xs, [stats dicts])."""

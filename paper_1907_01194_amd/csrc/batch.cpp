@@ -343,10 +343,11 @@ gpe_status ex_lap(gpe_batch* b, std::vector<Item>& g) {
 }
 
 // Batched HVP: fused x pass, projection coefficients, remaining axis passes
-// with the projection in the last one, kappa (same stages as hvp_enq).  Every
+// with the projection in the last one, kappa where wanted (same stages as
+// hvp_enq).  Every
 // launch's records are built first and staged with one copy.
 template <typename T>
-gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
+gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg, bool kappa) {
   gpe_handle* h0 = b->hs[0];
   const size_t m = g.size();
   std::vector<XpassArgs<T>> xr(m);
@@ -410,8 +411,8 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
       nq = 7 + a;
     }
   }
-  std::vector<FinArgs> fk;
-  GPE_TRY(fin_records(b, g, nq, gram, nb, true, cg, &fk));
+  std::vector<FinArgs> fk;   // the kappa finalize, where anyone reads kappa
+  if (kappa) GPE_TRY(fin_records(b, g, nq, gram, nb, true, cg, &fk));
 
   // one staging copy for every launch below
   const void *dx = nullptr, *dx0 = nullptr, *dab = nullptr, *dp = nullptr, *dp0 = nullptr, *dk = nullptr;
@@ -427,7 +428,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
     segs.push_back(seg(lr[a], &dl[a]));
     segs.push_back(seg(l0[a], &dl0[a]));
   }
-  segs.push_back(seg(fk, &dk));
+  if (kappa) segs.push_back(seg(fk, &dk));
   GPE_TRY(b->sg.put_all(h0, b->st, segs.data(), segs.size()));
 
   const int n = (int)m;
@@ -442,6 +443,7 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
   for (int a = 1; a < b->dim; ++a)
     GPE_HIP(h0, lap_batched<T>(reinterpret_cast<const LapArgs<T>*>(dl[a]),
                                Span{reinterpret_cast<const int*>(dl0[a]), n, l0[a].back()}, b->F, 6 + a, b->st));
+  if (!kappa) return GPE_OK;
   const int post = cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E;
   GPE_HIP(h0, finalize_batched(reinterpret_cast<const FinArgs*>(dk), n, nq, post, b->F, b->st));
   return GPE_OK;
@@ -449,12 +451,14 @@ gpe_status hvp_batched(gpe_batch* b, std::vector<Item>& g, bool riem, bool cg) {
 
 gpe_status ex_hvp(gpe_batch* b, std::vector<Item>& g) {
   if (!b || g.size() == 1) {
-    for (auto& it : g) GPE_TRY(hvp_enq(it.c->h, it.r->a, it.r->c, it.r->flag, it.r->s0, it.r->cg));
+    for (auto& it : g) GPE_TRY(hvp_enq(it.c->h, it.r->a, it.r->c, it.r->flag, it.r->s0, it.r->cg, it.r->kappa));
     return GPE_OK;
   }
   const bool riem = g[0].r->flag, cg = g[0].r->cg;
   if (cg && !riem) return fail(g[0].c->h, GPE_EINVAL, "the device-resident CG takes the Riemannian HVP");
-  return g[0].r->a32 ? hvp_batched<float>(b, g, riem, cg) : hvp_batched<double>(b, g, riem, cg);
+  bool kappa = cg;
+  for (auto& it : g) kappa = kappa || it.r->kappa;
+  return g[0].r->a32 ? hvp_batched<float>(b, g, riem, cg, kappa) : hvp_batched<double>(b, g, riem, cg, kappa);
 }
 
 gpe_status ex_cg(gpe_batch* b, std::vector<Item>& g) {
@@ -596,7 +600,7 @@ gpe_status Stager::put_all(gpe_handle* h, hipStream_t st, const Seg* segs, size_
   return GPE_OK;
 }
 
-gpe_status Lockstep::round(std::vector<Ctx*>& cs) {
+gpe_status Lockstep::round(std::vector<Ctx*>& cs, bool sync) {
   // Run the queues head by head, each step taking the operation that heads
   // the most queues: a problem's own order is kept and launches are shared.
   std::vector<size_t> head(cs.size(), 0);
@@ -624,6 +628,8 @@ gpe_status Lockstep::round(std::vector<Ctx*>& cs) {
       return s;
     }
   }
+  for (Ctx* c : cs) c->q.clear();
+  if (!sync) return GPE_OK;   // the staging arena keeps its place: its records may not be consumed yet
   gpe_handle* h0 = cs[0]->h;
   if (b_) {
     GPE_HIP(h0, hipMemcpyAsync(b_->hres, b_->res, sizeof(double) * kResDoubles * b_->hs.size(),
@@ -638,7 +644,6 @@ gpe_status Lockstep::round(std::vector<Ctx*>& cs) {
     GPE_HIP(c->h, hipStreamSynchronize(c->h->st));
   }
   if (b_) b_->sg.off = 0;
-  for (Ctx* c : cs) c->q.clear();
   return GPE_OK;
 }
 
@@ -857,11 +862,12 @@ gpe_status gpe_batch_hvp(gpe_batch* b, const void* const* Z, void* const* HZ, in
     r.flag = riemannian != 0;
     r.s0 = sigma ? sigma[i] : 0.0;
     r.a32 = r.c32 = b->prec == GPE_MIXED;
+    r.kappa = kappa != nullptr;
     cs[i].push(r);
     cp[i] = &cs[i];
   }
   Lockstep ls(b);
-  const gpe_status s = ls.round(cp);
+  const gpe_status s = ls.round(cp, kappa != nullptr);
   if (s != GPE_OK) return batch_fail(b, s, b->err.empty() ? b->hs[0]->err : b->err);
   if (kappa)
     for (size_t i = 0; i < m; ++i) {

@@ -87,6 +87,7 @@ __device__ void finalize_body(const double* __restrict__ part, size_t stride, co
         res[CG_KAPPA] = kappa;
         res[CG_PP] = pp;
         res[CG_REASON] = CG_STOP_CURVATURE;
+        res[CG_CURV] = 1.0;
         res[CG_DONE] = 1.0;
       } else {
         res[CG_ALPHA] = out[cg_rr_slot((int)out[CG_IT] - 1)] / kappa;   // (CG_IT counts this iteration already)
@@ -307,14 +308,15 @@ template <typename T>
 __device__ void run_op(const CgDirArgs<T>& a, int blk, int nblk) {
   double* c = a.res;
   if (c[CG_IT] != (double)(a.iter + 1)) return;   // the iteration stopped before its update, or never ran
-  const bool zupd = c[CG_REASON] != (double)CG_STOP_CURVATURE;
+  const bool zupd = c[CG_CURV] == 0.0;
   if (!zupd) return;   // a curvature stop: neither z nor p changes
   bool pupd;
   double bv;
   if (a.part) {
     // the residual and cap tests from the update's partials (uniform: every
     // workgroup sums them in the same order; workgroup 0 stores the outcome,
-    // in slots no workgroup of this launch reads)
+    // in slots no workgroup of this launch reads: CG_REASON, CG_DONE, CG_BETA
+    // and the next iteration's ||r||^2 slot)
     __shared__ double red[kRedThreads / kWave];
     double s = 0.0;
     for (int b = threadIdx.x; b < a.nb; b += blockDim.x) s += a.part[b];
@@ -384,6 +386,7 @@ __device__ void run_op(const CgInitArgs& a, int blk, int nblk) {
   double* c = a.res;
   c[CG_RR] = c[0];
   c[CG_RR1] = 0.0;
+  c[CG_CURV] = 0.0;
   c[CG_IT] = 0.0;
   c[CG_TOL] = a.tol;
   c[CG_EPS] = a.eps;

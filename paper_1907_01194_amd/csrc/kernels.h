@@ -129,7 +129,9 @@ enum CgSlot {
   CG_TOL,         // residual tolerance
   CG_EPS,         // curvature threshold factor: stop when kappa <= eps ||p||^2
   CG_MAXIT,       // iteration cap
-  CG_RR1
+  CG_RR1,
+  CG_CURV         // 1 once the curvature test stopped the CG (written only by the kappa finalize,
+                  // so the closing step can read it while its workgroup 0 writes CG_REASON)
 };
 // ||r||^2 at the start of iteration i (0-based) of the CG
 __host__ __device__ inline int cg_rr_slot(int i) { return (i & 1) ? CG_RR1 : CG_RR; }

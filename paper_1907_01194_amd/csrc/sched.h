@@ -49,6 +49,7 @@ struct Req {
   double* gram = nullptr;
   size_t n = 0;
   bool a32 = false, b32 = false, c32 = false, flag = false, cg = false;
+  bool kappa = true;   // RQ_HVP: form kappa = <Z, HZ> (always with cg)
 };
 
 // Coroutine of one problem's driver; its value is the problem's status.
@@ -125,8 +126,9 @@ class Lockstep {
  public:
   // batch: the batch the problems belong to (null for a lone handle).
   explicit Lockstep(::gpe_batch* batch) : b_(batch) {}
-  // Execute every queued request, bring all results to the host, synchronise.
-  gpe_status round(std::vector<Ctx*>& cs);
+  // Execute every queued request; with sync, bring all results to the host
+  // and synchronise, else leave the launches queued on the stream.
+  gpe_status round(std::vector<Ctx*>& cs, bool sync = true);
   // Resume the drivers round after round until every one has returned.
   gpe_status run(std::vector<Ctx*>& cs);
 

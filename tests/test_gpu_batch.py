@@ -49,7 +49,12 @@ def test_batch_hvp_matches_single_and_oracle(torch, precision):
         p.set_point(X)
     for riem in (True, False):
         HB, kap = b.hvp(Z, riemannian=riem, sigma=sig)
+        # without kappa: same products, no kappa finalize, no synchronisation
+        HB0, k0 = b.hvp(Z, riemannian=riem, sigma=sig, kappa=False)
         torch.cuda.synchronize()
+        assert k0 is None
+        for i in range(len(specs)):
+            assert torch.equal(HB0[i], HB[i]), (i, riem)
         for i, (p, sp) in enumerate(zip(b.problems, specs)):
             HS = p.hvp(Z[i], riemannian=riem, sigma=sig[i])
             tol_s = 1e-12 if precision == "fp64" else 2e-6
@@ -181,7 +186,10 @@ def test_batch_hvp_other_spins_and_dims(torch, F, dim, sizes):
     sig = [0.05] * len(specs)
     for riem in (True, False):
         HB, kap = b.hvp(dirs, riemannian=riem, sigma=sig)
+        HB0, _ = b.hvp(dirs, riemannian=riem, sigma=sig, kappa=False)
+        torch.cuda.synchronize()
         for i, p in enumerate(b.problems):
+            assert torch.equal(HB0[i], HB[i]), (i, riem)
             HS, k1 = p.hvp_dot(dirs[i], sigma=sig[i]) if riem else (p.hvp(dirs[i]), None)
             assert rel(host(HB[i]), host(HS)) <= 1e-12, (i, riem)
             if riem:
