@@ -41,9 +41,10 @@ template <typename T>
 __global__ void __launch_bounds__(LapB::THREADS)
 lap_batched_kernel(const LapArgs<T>* __restrict__ args, const int* __restrict__ blk0, int nprob, int F, int slot) {
   using T2 = c_t<T>;
-  const int pb = batch_problem(blk0, nprob);
+  const int gb = sizeof(T) == 4 ? xcd_local_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int pb = batch_problem(blk0, nprob, gb);
   const LapArgs<T>& a = args[pb];
-  const long blk = (long)blockIdx.x - blk0[pb];
+  const long blk = (long)gb - blk0[pb];
   switch (a.n) {
 #define GPE_CASE(NN)                                                                                          \
   case NN:                                                                                                    \
@@ -100,9 +101,10 @@ template <typename T, int F, int VAR>
 __global__ void __launch_bounds__((XB<2 * F + 1, VAR>::THREADS))
 xpass_batched_kernel(const XpassArgs<T>* __restrict__ args, const int* __restrict__ blk0, int nprob) {
   using T2 = c_t<T>;
-  const int pb = batch_problem(blk0, nprob);
+  const int gb = sizeof(T) == 4 ? xcd_local_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int pb = batch_problem(blk0, nprob, gb);
   const XpassArgs<T>& a = args[pb];
-  const long blk = (long)blockIdx.x - blk0[pb];
+  const long blk = (long)gb - blk0[pb];
   switch (a.n) {
 #define GPE_CASE(NN)                                                                                              \
   case NN:                                                                                                        \

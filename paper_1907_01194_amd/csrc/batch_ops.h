@@ -13,18 +13,20 @@
 
 namespace gpe {
 
-// Problem owning this workgroup: the last p with blk0[p] <= blockIdx.x
-// (one ballot per 64 problems).
-__device__ __forceinline__ int batch_problem(const int* __restrict__ blk0, int nprob) {
+// Problem owning workgroup b (default: this one): the last p with
+// blk0[p] <= b (one ballot per 64 problems).
+__device__ __forceinline__ int batch_problem(const int* __restrict__ blk0, int nprob, int b = -1) {
+  if (b < 0) b = (int)blockIdx.x;
   const int lane = threadIdx.x % kWave;
   int cnt = 0;
   for (int base = 0; base < nprob; base += kWave) {
     const int i = base + lane;
-    const bool le = i < nprob && blk0[i] <= (int)blockIdx.x;
+    const bool le = i < nprob && blk0[i] <= b;
     cnt += __popcll(__ballot(le));
   }
   return cnt - 1;
 }
+
 
 template <typename A>
 __global__ void __launch_bounds__(kRedThreads) op_kernel(A a) {

@@ -40,6 +40,16 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kRedThreads = 256;   // block size of reduction-producing kernels
 constexpr int kMaxQ = 32;          // partial sums per reduction launch (max)
 constexpr int kMaxRedBlocks = 2048;
+constexpr int kXcds = 8;           // accelerator dies (XCDs), each with its own L2
+
+// The hardware hands workgroup b of a launch to XCD b % kXcds.  Renumbered
+// this way, consecutive numbers share an XCD and its L2: workgroups that read
+// neighbouring parts of the same cache lines then find them there.  A
+// bijection on [0, nb) for any nb; workgroup 0 keeps number 0.
+__device__ __forceinline__ int xcd_local_block(int b, int nb) {
+  const int x = b % kXcds, i = b / kXcds, q = nb / kXcds, rem = nb % kXcds;
+  return x * q + (x < rem ? x : rem) + i;
+}
 
 // Sum of a double over the wavefront (shuffle tree).
 __device__ __forceinline__ double wave_sum(double v) {

@@ -24,7 +24,9 @@ lap_axis_kernel(const c_t<T>* __restrict__ in, const c_t<T>* acc, c_t<T>* out,
                 const c_t<T>* __restrict__ twg, long nlines, int inner, T lamc, int F, size_t npts,
                 const c_t<T>* __restrict__ X, const double* __restrict__ coef, double* __restrict__ part,
                 size_t stride, int slot, const double* skip, int rev, AbSrc ab, AbSrc fin) {
-  long b = (long)blockIdx.x;
+  // c64 lines: consecutive workgroups on one XCD (measured faster for c64
+  // and slower for c128, whose line segments already fill the cache lines)
+  long b = sizeof(T) == 4 ? (long)xcd_local_block((int)blockIdx.x, (int)gridDim.x) : (long)blockIdx.x;
   long nb = (long)gridDim.x;
   if (fin.part) {
     if (b == 0) {
@@ -45,7 +47,8 @@ __global__ void __launch_bounds__((XGeo<N, 2 * F + 1, VAR>::THREADS))
 hvp_xpass_kernel(const c_t<T>* __restrict__ X, const c_t<T>* __restrict__ Z, const c_t<T>* __restrict__ Y,
                  const T* __restrict__ V, c_t<T>* __restrict__ W, const c_t<T>* __restrict__ twg, long nrows,
                  size_t npts, T lamc, PwParams p, double* __restrict__ part, size_t stride, const double* skip) {
-  xpass_body<T, N, F, VAR>(X, Z, Y, V, W, twg, nrows, npts, lamc, p, part, stride, blockIdx.x, skip);
+  const long blk = sizeof(T) == 4 ? (long)xcd_local_block((int)blockIdx.x, (int)gridDim.x) : (long)blockIdx.x;
+  xpass_body<T, N, F, VAR>(X, Z, Y, V, W, twg, nrows, npts, lamc, p, part, stride, blk, skip);
 }
 
 template <typename T, int N>
