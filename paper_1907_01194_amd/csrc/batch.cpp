@@ -70,7 +70,7 @@ gpe_status fin_records(gpe_batch* b, const std::vector<Item>& g, int nq, const s
     const size_t stride = pstride ? h->pstride : (size_t)h->nblk;
     for (int q = 0; q < nq; ++q)
       if (nb[i].nb[q] < 0 || (size_t)nb[i].nb[q] > stride) return fail(h0, GPE_EINVAL, "finalize: slot count");
-    (*recs)[i] = FinArgs{h->part, h->res, gram[i], h->ticket, stride, nb[i], cg ? h->res + CG_DONE : nullptr};
+    (*recs)[i] = FinArgs{h->part, h->res, gram[i], stride, nb[i], cg ? h->res + CG_DONE : nullptr};
   }
   return GPE_OK;
 }

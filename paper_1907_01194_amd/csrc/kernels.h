@@ -137,10 +137,9 @@ enum CgSlot {
 __host__ __device__ inline int cg_rr_slot(int i) { return (i & 1) ? CG_RR1 : CG_RR; }
 enum CgStop { CG_STOP_NONE = 0, CG_STOP_CURVATURE = 1, CG_STOP_RESIDUAL = 2, CG_STOP_CAP = 3 };
 // Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
-// (deterministic), then apply `post`.  ticket: a device counter that is 0
-// between launches (the launch leaves it at 0).
+// (deterministic; one workgroup), then apply `post`.
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post,
-                    int F, double* gram, unsigned int* ticket, const double* skip, hipStream_t st);
+                    int F, double* gram, const double* skip, hipStream_t st);
 
 // out_i = W_i - (coef[0] + coef[1] l_i) X_i (coef on the device).  X is c128
 // or c64 as TX; W/out in T.  If part != null, partial sums of ||out||^2 (nq = 1).
@@ -303,12 +302,11 @@ template <typename A> hipError_t launch_batched(const A* args, const Span& sp, h
 int elementwise_blocks(size_t total);
 
 // Batched finalize: problem p sums args[p].part (stride args[p].stride, counts
-// args[p].nb) into args[p].res with its own ticket and gram; grid (nq, nprob).
+// args[p].nb) into args[p].res with its own gram; one workgroup per problem.
 struct FinArgs {
   const double* part;
   double* res;
   double* gram;
-  unsigned int* ticket;
   size_t stride;
   SlotCounts nb;
   const double* skip;

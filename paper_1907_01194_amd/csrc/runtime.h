@@ -36,7 +36,6 @@ struct gpe_handle {
   double* gram_tmp = nullptr;  // scratch gram (7)
   double* hres = nullptr;      // pinned host mirror of res
   bool res_shared = false;     // res / hres are slices of a batch's arrays (not owned)
-  unsigned int* ticket = nullptr;  // finalize completion counter (0 between launches)
   int nblk = 1;
   int xvar = 1;                // schedule variant of the fused x pass (autotuned)
   float xvar_us[3] = {0, 0, 0};  // measured microseconds per variant (0: not measured)
