@@ -353,7 +353,7 @@ def batch_measure(count, steps, solve, sequential, log):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     def timed(fn):
-        for _ in range(5):
+        for _ in range(20):
             fn()
         torch.cuda.synchronize()
         e0.record(stream)
@@ -590,7 +590,7 @@ def main():
               flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batched": batch_measure(args.batch_count, 50, not args.no_batch_solve,
+        print(json.dumps({"batched": batch_measure(args.batch_count, 200, not args.no_batch_solve,
                                                    not args.no_batch_sequential, log)}), flush=True)
         return
     from paper_1907_01194_amd import workloads as W
@@ -628,7 +628,7 @@ def main():
         entry["to_1e-5_relative_energy"] = time_to_accuracy(entry, precs)
         solves["benchmark_physics"] = entry
         solves["configs"] = config_solves(log)
-    batch = None if args.no_batch else batch_measure(args.batch_count, 50, not args.no_batch_solve,
+    batch = None if args.no_batch else batch_measure(args.batch_count, 200, not args.no_batch_solve,
                                                      not args.no_batch_sequential, log)
     cpu = None
     if not args.no_cpu:
