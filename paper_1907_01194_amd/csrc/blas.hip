@@ -8,45 +8,82 @@
 namespace gpe {
 
 // ----------------------------------------------------------------- finalize
-// One workgroup per problem.  Its waves split the slots (several waves per
-// slot when there are fewer slots than waves); each lane sums a fixed strided
-// subset of a slot's partials, each wave a fixed shuffle tree, and thread 0
-// adds the waves of a slot in order: bitwise reproducible.  Thread 0 stores the
-// sums and applies the post-operation.  No atomics, no cross-workgroup fence.
-constexpr int kFinThreads = 1024;
+// Two forms, both summing in a fixed order (bitwise reproducible):
+// * one workgroup (ticket null): its waves split the slots (several waves per
+//   slot when there are fewer slots than waves); each lane sums a fixed strided
+//   subset of a slot's partials, each wave a fixed shuffle tree, and thread 0
+//   adds the waves of a slot in order, stores the sums and applies the
+//   post-operation.  No atomics, no cross-workgroup fence.
+// * one workgroup per slot (ticket non-null, slot q = the workgroup's index):
+//   for many partials, where one workgroup cannot fetch them fast enough.  The
+//   last workgroup to finish (counted with the atomic ticket, which it resets)
+//   applies the post-operation.
+constexpr int kFinThreads = 1024;   // up to 16k partials per slot: 16 loads per thread
 constexpr int kFinWaves = kFinThreads / kWave;
+constexpr int kFinOneBlockMax = 1024;   // partials per slot up to which one workgroup does all
 
 __device__ void finalize_body(const double* __restrict__ part, size_t stride, const SlotCounts& nb, int nq,
-                              double* __restrict__ res, int post, int F, double* gram, const double* skip) {
+                              double* __restrict__ res, int post, int F, double* gram, unsigned int* ticket,
+                              const double* skip) {
   __shared__ double red[kMaxQ > kFinWaves ? kMaxQ : kFinWaves];
-  if (skip && *skip != 0.0) return;   // uniform over the workgroup
+  __shared__ bool last;
+  if (skip && *skip != 0.0) return;   // uniform over the launch: no ticket is taken
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int wps = nq < kFinWaves ? kFinWaves / nq : 1;   // waves per slot; nq * wps <= max(nq, kFinWaves)
-  for (int q = w / wps; q < nq; q += kFinWaves / wps) {
-    const int sub = w % wps;
+  if (ticket) {
+    const int q = blockIdx.x;
     const double* pq = part + (size_t)q * stride;
     const int n = nb.nb[q];
-    const int step = wps * kWave;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    int b = sub * kWave + lane;
-    for (; b + 3 * step < n; b += 4 * step) {
+    int b = threadIdx.x;
+    for (; b + 3 * kFinThreads < n; b += 4 * kFinThreads) {
       s0 += pq[b];
-      s1 += pq[b + step];
-      s2 += pq[b + 2 * step];
-      s3 += pq[b + 3 * step];
+      s1 += pq[b + kFinThreads];
+      s2 += pq[b + 2 * kFinThreads];
+      s3 += pq[b + 3 * kFinThreads];
     }
-    for (; b < n; b += step) s0 += pq[b];
+    for (; b < n; b += kFinThreads) s0 += pq[b];
     const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) red[q * wps + sub] = s;
+    if (lane == 0) red[w] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int u = 0; u < kFinWaves; ++u) t += red[u];
+      res[q] = t;
+      __threadfence();
+      last = atomicAdd(ticket, 1u) == (unsigned)(nq - 1);
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    *ticket = 0u;   // every workgroup of this launch has taken its ticket
+    __threadfence();
+  } else {
+    const int wps = nq < kFinWaves ? kFinWaves / nq : 1;   // waves per slot; nq * wps <= max(nq, kFinWaves)
+    for (int q = w / wps; q < nq; q += kFinWaves / wps) {
+      const int sub = w % wps;
+      const double* pq = part + (size_t)q * stride;
+      const int n = nb.nb[q];
+      const int step = wps * kWave;
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      int b = sub * kWave + lane;
+      for (; b + 3 * step < n; b += 4 * step) {
+        s0 += pq[b];
+        s1 += pq[b + step];
+        s2 += pq[b + 2 * step];
+        s3 += pq[b + 3 * step];
+      }
+      for (; b < n; b += step) s0 += pq[b];
+      const double s = wave_sum((s0 + s1) + (s2 + s3));
+      if (lane == 0) red[q * wps + sub] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < nq; ++q) {
+      double t = 0.0;
+      for (int u = 0; u < wps; ++u) t += red[q * wps + u];
+      res[q] = t;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int q = 0; q < nq; ++q) {
-    double t = 0.0;
-    for (int u = 0; u < wps; ++u) t += red[q * wps + u];
-    res[q] = t;
-  }
-  const double* out = res;
+  const volatile double* out = res;   // (slots written by other workgroups in the ticket form)
   const int K = 2 * F + 1;
   if (post == POST_GRAD) {
     // Gram system of Lemma 4.1 (proof) with the measured u^T u, u^T G u, u^T G^2 u
@@ -114,14 +151,14 @@ __device__ void finalize_body(const double* __restrict__ part, size_t stride, co
 
 __global__ void __launch_bounds__(kFinThreads)
 finalize_kernel(const double* __restrict__ part, size_t stride, SlotCounts nb, int nq, double* __restrict__ res,
-                int post, int F, double* gram, const double* skip) {
-  finalize_body(part, stride, nb, nq, res, post, F, gram, skip);
+                int post, int F, double* gram, unsigned int* ticket, const double* skip) {
+  finalize_body(part, stride, nb, nq, res, post, F, gram, ticket, skip);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
 finalize_batched_kernel(const FinArgs* __restrict__ args, int nq, int post, int F) {
   const FinArgs& a = args[blockIdx.x];
-  finalize_body(a.part, a.stride, a.nb, nq, a.res, post, F, a.gram, a.skip);
+  finalize_body(a.part, a.stride, a.nb, nq, a.res, post, F, a.gram, nullptr, a.skip);
 }
 
 static bool counts_ok(const SlotCounts& nb, int nq, size_t stride) {
@@ -132,10 +169,13 @@ static bool counts_ok(const SlotCounts& nb, int nq, size_t stride) {
 }
 
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post, int F,
-                    double* gram, const double* skip, hipStream_t st) {
+                    double* gram, unsigned int* ticket, const double* skip, hipStream_t st) {
   if (!counts_ok(nb, nq, stride)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, st, part, stride, nb, nq, res, post, F, gram,
-                     skip);
+  int most = 0;
+  for (int q = 0; q < nq; ++q) most = nb.nb[q] > most ? nb.nb[q] : most;
+  const bool split = ticket && most > kFinOneBlockMax;
+  hipLaunchKernelGGL(finalize_kernel, dim3(split ? nq : 1), dim3(kFinThreads), 0, st, part, stride, nb, nq, res, post,
+                     F, gram, split ? ticket : nullptr, skip);
   return hipGetLastError();
 }
 

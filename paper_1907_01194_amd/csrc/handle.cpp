@@ -63,7 +63,7 @@ template gpe_status laplacian<float>(gpe_handle*, const void*, void*);
 gpe_status finalize_enq(gpe_handle* h, int nq, int post, double* gram) {
   SlotCounts nb;
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = h->nblk;
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, nullptr, h->st));
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, nq, h->res, post, h->F, gram, h->ticket, nullptr, h->st));
   return GPE_OK;
 }
 
@@ -178,7 +178,7 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   const bool ab_ypass = riem && !ab_local && h->dim == 3;
   if (riem && !ab_local && !ab_ypass)
     GPE_KT(h, KK_FINALIZE,
-           finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, skip, h->st));
+           finalize(h->part, h->pstride, nb, 7, h->res, POST_HVP_AB, h->F, h->gram_pt, h->ticket, skip, h->st));
   int nq = 7;
   if (h->dim == 1) {
     // (after a CG stop this projection still runs, on an HZ that nothing reads any more)
@@ -200,7 +200,7 @@ static gpe_status hvp_t(gpe_handle* h, const void* Z, void* HZ, bool riem, const
   }
   if (!cg && !kappa) return GPE_OK;
   const int post = cg ? POST_CG_KAPPA : riem ? POST_HVP_KAPPA : POST_HVP_KAPPA_E;
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, post, h->F, h->gram_pt, skip, h->st));
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->pstride, nb, nq, h->res, post, h->F, h->gram_pt, h->ticket, skip, h->st));
   return GPE_OK;
 }
 
@@ -403,7 +403,7 @@ static gpe_status cg_step_t(gpe_handle* h, const void* p, const void* q, void* z
   if (cg_local_step(h)) return GPE_OK;
   SlotCounts nb;
   for (int k = 0; k < kMaxQ; ++k) nb.nb[k] = h->nblk;
-  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, 1, h->res, POST_CG_STEP, h->F, nullptr,
+  GPE_KT(h, KK_FINALIZE, finalize(h->part, h->nblk, nb, 1, h->res, POST_CG_STEP, h->F, nullptr, h->ticket,
                                   h->res + CG_DONE, h->st));
   return GPE_OK;
 }
@@ -517,13 +517,13 @@ static std::string problem_error(const gpe_problem* pr) {
 }
 
 // ----------------------------------------------------------------- scratch of gpe_retract_noalloc
-// The retraction's partial sums (3K slots of at most kMaxRedBlocks workgroups)
-// and the finalize's results, for every admissible problem.  One
+// The retraction's partial sums (3K slots of at most kMaxRedBlocks workgroups),
+// the finalize's results and its ticket, for every admissible problem.  One
 // copy per GPU, at a device address found once per device.
 namespace {
 constexpr size_t kNaPart = 3 * 7 * (size_t)kMaxRedBlocks;
 constexpr size_t kNaRes = 64;
-constexpr size_t kNaDoubles = kNaPart + kNaRes;
+constexpr size_t kNaDoubles = kNaPart + kNaRes + 2;   // + the ticket (first 4 bytes of the last 16)
 constexpr int kNaMaxDevices = 64;
 }  // namespace
 static __device__ __align__(256) double scratch[kNaDoubles];
@@ -599,7 +599,7 @@ gpe_status gpe_destroy(gpe_handle* h) {
     if (h->res) (void)hipFree(h->res);
     if (h->hres) (void)hipHostFree(h->hres);
   }
-  void* bufs[] = {h->V64, h->V32, h->part, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
+  void* bufs[] = {h->ticket, h->V64, h->V32, h->part, h->gram_pt, h->gram_tmp, h->T64, h->T32, h->Xp, h->Gp, h->Xp32,
                   h->LX64, h->LX32,
                   h->tw[0], h->tw[1], h->tw[2], h->tw[3], h->tw[4], h->tw[5]};
   for (void* b : bufs)
@@ -710,6 +710,7 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V, int precision, voi
   GPE_ALLOC(h->res, sizeof(double) * kResDoubles);
   GPE_ALLOC(h->gram_pt, sizeof(double) * 8);
   GPE_ALLOC(h->gram_tmp, sizeof(double) * 8);
+  GPE_ALLOC(h->ticket, sizeof(unsigned int) * 4);
   GPE_ALLOC(h->T64, f64);
   GPE_ALLOC(h->Xp, f64);
   GPE_ALLOC(h->Gp, f64);
@@ -731,7 +732,9 @@ gpe_status gpe_create(const gpe_problem* pr, const double* V, int precision, voi
     gpe_destroy(h);
     return GPE_EHIP;
   };
-  hipError_t e = hipMemcpyAsync(h->V64, V_host, h->npts * sizeof(double), hipMemcpyHostToDevice, h->st);
+  hipError_t e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int) * 4, h->st);
+  if (e != hipSuccess) return bail(e, "clear ticket");
+  e = hipMemcpyAsync(h->V64, V_host, h->npts * sizeof(double), hipMemcpyHostToDevice, h->st);
   if (e != hipSuccess) return bail(e, "copy V");
   if (precision == GPE_MIXED) {
     std::vector<float> v32(h->npts);
@@ -943,16 +946,19 @@ gpe_status gpe_retract_noalloc(const gpe_problem* pr, const void* X, const void*
   GPE_TRY(scratch_on_device(&base));
   double* part = base;
   double* res = base + kNaPart;
+  unsigned int* ticket = reinterpret_cast<unsigned int*>(base + kNaPart + kNaRes);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 #define NA_HIP(call)                                                  \
   do {                                                                \
     hipError_t e_ = (call);                                           \
     if (e_ != hipSuccess) return hip_fail(nullptr, e_, #call);        \
   } while (0)
+  // the ticket starts at 0 (a finalize leaves it there; an interrupted call might not)
+  NA_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned int), st));
   NA_HIP((comp_norms<double, double>(K, X, Xi, part, nblk, npts, st)));
   SlotCounts nb;
   for (int q = 0; q < kMaxQ; ++q) nb.nb[q] = nblk;
-  NA_HIP(finalize(part, nblk, nb, nq, res, POST_NONE, F, nullptr, nullptr, st));
+  NA_HIP(finalize(part, nblk, nb, nq, res, POST_NONE, F, nullptr, ticket, nullptr, st));
   double r[3 * 7];
   NA_HIP(hipMemcpyAsync(r, res, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
   NA_HIP(hipStreamSynchronize(st));

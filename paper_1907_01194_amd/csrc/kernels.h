@@ -137,9 +137,11 @@ enum CgSlot {
 __host__ __device__ inline int cg_rr_slot(int i) { return (i & 1) ? CG_RR1 : CG_RR; }
 enum CgStop { CG_STOP_NONE = 0, CG_STOP_CURVATURE = 1, CG_STOP_RESIDUAL = 2, CG_STOP_CAP = 3 };
 // Sum partials part[q * stride + b], b < nb[q], for q < nq into res[q]
-// (deterministic; one workgroup), then apply `post`.
+// (deterministic), then apply `post`.  One workgroup, or with many partials
+// one per slot; ticket (may be null: always one workgroup) is a device counter
+// that is 0 between launches (the launch leaves it at 0).
 hipError_t finalize(const double* part, size_t stride, const SlotCounts& nb, int nq, double* res, int post,
-                    int F, double* gram, const double* skip, hipStream_t st);
+                    int F, double* gram, unsigned int* ticket, const double* skip, hipStream_t st);
 
 // out_i = W_i - (coef[0] + coef[1] l_i) X_i (coef on the device).  X is c128
 // or c64 as TX; W/out in T.  If part != null, partial sums of ||out||^2 (nq = 1).

@@ -34,6 +34,7 @@ struct gpe_handle {
   double* res = nullptr;       // kResDoubles doubles
   double* gram_pt = nullptr;   // ||u_i||^2 of the set point (7)
   double* gram_tmp = nullptr;  // scratch gram (7)
+  unsigned int* ticket = nullptr;  // finalize completion counter (0 between launches)
   double* hres = nullptr;      // pinned host mirror of res
   bool res_shared = false;     // res / hres are slices of a batch's arrays (not owned)
   int nblk = 1;
