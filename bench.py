@@ -43,40 +43,40 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes), by precision and
 # schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": "665e4ccdd92b8ea9",
+    "src_hash": "ea25f777a76b97bf",
     "traffic": {
         "fp64": {
             "0": {
-                "hvp_xpass": 960318901,
-                "lap_axis_y": 705329686,
-                "lap_axis_z": 939957037
+                "hvp_xpass": 960305941,
+                "lap_axis_y": 705198546,
+                "lap_axis_z": 939952110
             },
             "1": {
-                "hvp_xpass": 958502622,
-                "lap_axis_y": 705329686,
-                "lap_axis_z": 939957037
+                "hvp_xpass": 958477089,
+                "lap_axis_y": 705198546,
+                "lap_axis_z": 939952110
             },
             "2": {
-                "hvp_xpass": 957680453,
-                "lap_axis_y": 705329686,
-                "lap_axis_z": 939957037
+                "hvp_xpass": 957670519,
+                "lap_axis_y": 705198546,
+                "lap_axis_z": 939952110
             }
         },
         "mixed": {
             "0": {
-                "hvp_xpass": 482111799,
-                "lap_axis_y": 352855956,
-                "lap_axis_z": 470162608
+                "hvp_xpass": 479323384,
+                "lap_axis_y": 352821751,
+                "lap_axis_z": 469991248
             },
             "1": {
-                "hvp_xpass": 481762173,
-                "lap_axis_y": 352855956,
-                "lap_axis_z": 470162608
+                "hvp_xpass": 478847786,
+                "lap_axis_y": 352821751,
+                "lap_axis_z": 469991248
             },
             "2": {
-                "hvp_xpass": 479390402,
-                "lap_axis_y": 352855956,
-                "lap_axis_z": 470162608
+                "hvp_xpass": 478603259,
+                "lap_axis_y": 352821751,
+                "lap_axis_z": 469991248
             }
         }
     },
@@ -87,9 +87,9 @@ MEASURED = {
             "2": 64040960
         },
         "mixed": {
-            "0": 66830336,
-            "1": 66527232,
-            "2": 63459328
+            "0": 66453504,
+            "1": 66240512,
+            "2": 63242240
         }
     }
 }
