@@ -140,6 +140,8 @@ def parse():
                     help="only reproduce the ARNT rows of the Sec. 7.1 tables (every magnetization, R1/R2/R3)")
     ap.add_argument("--tables", default="", help="with --paper-tables: comma list of tables (default: all)")
     ap.add_argument("--table-cap", type=float, default=120.0, help="with --paper-tables: seconds per solve")
+    ap.add_argument("--table-mg", type=int, default=0,
+                    help="with --paper-tables: coarser meshes of the cascadic hierarchy (0: one mesh)")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the paper's spin-3 128^3 ground-state solve (for profiling the whole solve)")
     ap.add_argument("--batch-only", action="store_true",
@@ -426,11 +428,12 @@ def batch_measure(count, steps, solve, sequential, log):
     return out
 
 
-def paper_tables(log, tables=None, cap=120.0):
+def paper_tables(log, tables=None, cap=120.0, mg=0):
     """ARNT on the Sec. 7.1 workloads (Tables 1-1-2 .. 1-3-3): every printed
-    magnetization with the three retractions, FP64, one mesh, ||grad|| <= 1e-6,
-    the paper's initial data.  Energies against the printed ones; times are this
-    GPU's (the paper's: MATLAB on a 12-core Xeon, all meshes)."""
+    magnetization with the three retractions, FP64, ||grad|| <= 1e-6, the
+    paper's initial data, on one mesh (mg = 0) or after mg coarser meshes of the
+    cascadic hierarchy (Algorithm 1).  Energies against the printed ones; times
+    are this GPU's (the paper's: MATLAB on a 12-core Xeon, all meshes)."""
     import torch
     from paper_1907_01194_amd import workloads as W
     from paper_1907_01194_amd.binding import Problem
@@ -445,19 +448,21 @@ def paper_tables(log, tables=None, cap=120.0):
                 X = torch.from_numpy(X0).cuda()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, st = gp.newton_solve(X, check=False, tol=1e-6, retraction=retr, time_limit=cap)
+                _, st = gp.newton_solve(X, check=False, tol=1e-6, retraction=retr, time_limit=cap, mg_levels=mg)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 gp.close()
                 del X
                 torch.cuda.empty_cache()
                 inner = st["cg_total"] / max(st["outer"], 1)
-                rows.append({"table": table, "M": M, "retraction": "R%d" % retr, "E": st["E"], "E_paper": E_paper,
+                rows.append({"table": table, "M": M, "retraction": "R%d" % retr, "mg_levels": st["mg_levels"],
+                             "E": st["E"], "E_paper": E_paper,
                              "dE": st["E"] - E_paper, "gnorm": st["gnorm"], "converged": bool(st["converged"]),
                              "outer": st["outer"], "avg_inner": round(inner, 1), "rgbb_iters": st["rgbb_iters"],
                              "seconds": round(dt, 3)})
-                log("table %s M=%g R%d: E=%.6f (paper %.4f, diff %+.1e) |g|=%.1e iter %d (%.0f) %.2fs" % (
-                    table, M, retr, st["E"], E_paper, st["E"] - E_paper, st["gnorm"], st["outer"], inner, dt))
+                log("table %s M=%g R%d mg=%d: E=%.6f (paper %.4f, diff %+.1e) |g|=%.1e iter %d (%.0f) %.2fs" % (
+                    table, M, retr, st["mg_levels"], st["E"], E_paper, st["E"] - E_paper, st["gnorm"], st["outer"],
+                    inner, dt))
     return rows
 
 
@@ -585,9 +590,9 @@ def main():
         copy_calibration(log)
         return
     if args.paper_tables:
-        rows = paper_tables(log, [t for t in args.tables.split(",") if t], args.table_cap)
-        print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6, "cap_s": args.table_cap}),
-              flush=True)
+        rows = paper_tables(log, [t for t in args.tables.split(",") if t], args.table_cap, args.table_mg)
+        print(json.dumps({"paper_tables": rows, "precision": "fp64", "tol": 1e-6, "cap_s": args.table_cap,
+                          "mg_levels": args.table_mg}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batched": batch_measure(args.batch_count, 200, not args.no_batch_solve,
