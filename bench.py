@@ -493,6 +493,29 @@ def cpu_baseline(spec, w, noise, log, reps=5):
             "seconds_per_hvp": round(dt, 3), "seconds_each": [round(t, 3) for t in ts]}
 
 
+def oracle_hvp_seconds(spec, seed, reps=3):
+    """The oracle's median time per Riemannian HVP (all host cores for
+    scipy.fft) at a point of `spec` built from its seeded initial state."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import oracle
+    import oracle.energy as oe
+    from paper_1907_01194_amd import workloads as W
+    oe.FFT_WORKERS = os.cpu_count()
+    prob = oracle.make_problem(spec.F, spec.n, spec.lo, spec.hi, spec.V, spec.beta, spec.M, spec.p, spec.q)
+    u = oracle.retraction.psi(prob, W.initial_state(spec, seed), 1)
+    xi = oracle.project(prob, u, W.random_direction(spec, 100 + seed))
+    xi /= np.sqrt(oracle.inner(xi, xi))
+    ag, bg = oracle.proj_coeffs(prob, u, oracle.grad(prob, u))
+    oracle.rhess(prob, u, xi, ag, bg, 1e-2)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.rhess(prob, u, xi, ag, bg, 1e-2)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
 def oracle_solves(log):
     """The oracle's own time-to-ground-state on the small configurations (all
     host cores for scipy.fft): spin-1 1D 128 to ||grad|| <= 1e-8 and spin-2 2D
@@ -643,6 +666,15 @@ def main():
             orc = oracle_solves(log)
         else:
             orc = {k: v for k, v in oracle_solves_small(log).items()}
+        c2 = solves.get("configs", {}).get("spin2-2d-256") if solves else None
+        if c2 and "spin2-2d-256" not in orc:
+            t2 = oracle_hvp_seconds(W.spin2_2d(), 2)
+            log("cpu oracle: %.4f s per HVP at spin-2 2D 256^2" % t2)
+            orc["spin2-2d-256 (estimate)"] = {
+                "kind": "estimate: oracle seconds per HVP (median of 3) x the GPU FP64 solve's HVP count (not run; "
+                        "bench.py --oracle-solves runs it)",
+                "seconds": round(t2 * c2["hvp_calls"], 1), "seconds_per_hvp": round(t2, 4),
+                "hvp_calls": c2["hvp_calls"]}
         fp = solves.get("benchmark_physics", {}).get("fp64") if solves else None
         if fp:
             orc["spin3-3d-128 (estimate)"] = {
