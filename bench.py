@@ -283,27 +283,31 @@ def roofline(spec, prec, ms, kt, variant, steps):
             "us_per_hvp": round(ms * 1e3, 2), "dominant_kernel": kern}
 
 
-def time_solve(spec, prec, w, limit, log, tol=1e-6, trace=0):
+def time_solve(spec, prec, w, limit, log, tol=1e-6, trace=0, mg=0):
     """Time-to-ground-state: newton_solve from w (device-resident before the
-    clock starts) to ||grad|| <= tol, or until `limit` seconds."""
+    clock starts) to ||grad|| <= tol, or until `limit` seconds; on one mesh, or
+    after mg coarser meshes of the cascadic hierarchy (Algorithm 1)."""
     import torch
     from paper_1907_01194_amd.binding import Problem
     gp = Problem(spec, prec)
     X = torch.from_numpy(w).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    X, st = gp.newton_solve(X, check=False, tol=tol, time_limit=limit, trace=trace)
+    X, st = gp.newton_solve(X, check=False, tol=tol, time_limit=limit, trace=trace, mg_levels=mg)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log("solve %s %s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
-        spec.name, prec, st["E"], st["gnorm"], st["converged"], st["rgbb_iters"], st["outer"], st["cg_total"],
-        st["hvp_calls"], wall))
+    log("solve %s %s%s: E=%.12f |g|=%.2e conv=%d rgbb=%d outer=%d cg=%d hvp=%d %.1fs" % (
+        spec.name, prec, " mg=%d" % st["mg_levels"] if mg else "", st["E"], st["gnorm"], st["converged"],
+        st["rgbb_iters"], st["outer"], st["cg_total"], st["hvp_calls"], wall))
     gp.close()
     del gp
     torch.cuda.empty_cache()
     out = {"seconds": round(wall, 3), "E": st["E"], "gnorm": st["gnorm"], "converged": bool(st["converged"]),
            "rgbb_iters": st["rgbb_iters"], "outer": st["outer"], "cg_total": st["cg_total"],
            "hvp_calls": st["hvp_calls"], "t_rgbb": round(st["t_rgbb"], 3), "t_arnt": round(st["t_arnt"], 3)}
+    if mg:
+        out.update({"mg_levels": st["mg_levels"], "t_coarse": round(st["t_coarse"], 3),
+                    "finest_mesh": {"outer": st["outer"], "cg_total": st["cg_total"], "hvp_calls": st["hvp_calls"]}})
     if trace:
         out["_trace"] = st["trace"]
     return out
@@ -323,7 +327,8 @@ def time_to_accuracy(entry, precs, rel=1e-5):
                 if abs(row[1] - Eref) <= rel * abs(Eref):
                     hit = row
                     break
-        out[p] = None if hit is None else {"seconds": round(float(hit[0]), 3), "hvp_calls": int(hit[3])}
+        t0 = entry[p].get("t_coarse", 0.0)   # a cascadic trace covers the finest mesh only
+        out[p] = None if hit is None else {"seconds": round(t0 + float(hit[0]), 3), "hvp_calls": int(hit[3])}
     return out
 
 
@@ -568,7 +573,7 @@ def config_solves(log):
     return out
 
 
-def paper_case_solves(n, precs, log):
+def paper_case_solves(n, precs, log, mg=0):
     """The paper's spin-3 128^3 workload (Sec. 7.3 Table 4-1 3D / Table 1-3-3, Case II, M = 0.5)
     from the paper's initial data, solved to ||grad|| <= 1e-6 in each precision."""
     from paper_1907_01194_amd import workloads as W
@@ -578,22 +583,26 @@ def paper_case_solves(n, precs, log):
              "paper_energy": 42.9822,
              "paper_context": {"seconds": 1050.1, "hardware": "MATLAB R2018b, 12-core Xeon E5-2680 v3",
                                "source": "Sec. 7.1 Table 1-3-3, ARNT with R1, M = 0.5, all meshes"}}
+    if mg:
+        entry["meshes"] = "cascadic: %s" % " -> ".join("%d^3" % (n >> (mg - i)) for i in range(mg + 1))
     for prec in precs:
-        entry[prec] = time_solve(ps, prec, pw, 300.0, log)
+        entry[prec] = time_solve(ps, prec, pw, 300.0, log, mg=mg)
         entry[prec]["energy_err_vs_paper"] = abs(entry[prec]["E"] - 42.9822)
     return entry
 
 
-def benchmark_physics_solves(spec, precs, limit, log, trace=4000):
+def benchmark_physics_solves(spec, precs, limit, log, trace=4000, mg=0):
     """The benchmark physics (beta = (500, 5, -5, 2), gamma = (1, 1, 2)) from the
     Sec. 7 kind of initial data, each precision to ||grad|| <= 1e-6 or the
-    time cap, with the time each takes to reach 1e-5 relative energy."""
+    time cap (on one mesh, or after mg coarser meshes of the cascadic
+    hierarchy), with the time each takes to reach 1e-5 relative energy."""
     from paper_1907_01194_amd import workloads as W
     bw = W.paper_initial(spec, W.paper_U(3, None, spec.M, 3))
     entry = {"workload": spec.name, "initial": "U phi0, U seeded uniform in R^7 (Sec. 7)", "tol": 1e-6,
-             "time_cap_s": limit}
+             "time_cap_s": limit, "meshes": "one (%d^3)" % spec.n[0] if not mg else
+             "cascadic: %s" % " -> ".join("%d^3" % (spec.n[0] >> (mg - i)) for i in range(mg + 1))}
     for prec in precs:
-        entry[prec] = time_solve(spec, prec, bw, limit, log, trace=trace)
+        entry[prec] = time_solve(spec, prec, bw, limit, log, trace=trace, mg=mg)
     return entry
 
 
@@ -655,6 +664,11 @@ def main():
         entry = benchmark_physics_solves(spec, precs, args.solve_time, log)
         entry["to_1e-5_relative_energy"] = time_to_accuracy(entry, precs)
         solves["benchmark_physics"] = entry
+        # Algorithm 1's cascadic outer loop: three coarser meshes (16^3 .. 64^3) first
+        solves["paper_case_cascadic"] = paper_case_solves(args.n, precs, log, mg=3)
+        cas = benchmark_physics_solves(spec, precs, args.solve_time, log, mg=3)
+        cas["to_1e-5_relative_energy"] = time_to_accuracy(cas, precs)
+        solves["benchmark_physics_cascadic"] = cas
         solves["configs"] = config_solves(log)
     batch = None if args.no_batch else batch_measure(args.batch_count, 200, not args.no_batch_solve,
                                                      not args.no_batch_sequential, log)
