@@ -423,6 +423,23 @@ def batch_measure(count, steps, solve, sequential, log):
         out["solve"] = {"tol": 1e-6, "batched_s": round(tb, 3), "converged": conv,
                         "max_hvp_calls": max(s["hvp_calls"] for s in st),
                         "total_hvp_calls": sum(s["hvp_calls"] for s in st)}
+        # the same batch through the cascadic hierarchy (two coarser meshes per problem, each level in lock step)
+        Xc = [x.clone() for x in X0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, stc = b.newton_solve(Xc, check=False, tol=1e-6, mg_levels=2)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        convc = sum(int(s["converged"]) for s in stc)
+        dEc = max(abs(a["E"] - c["E"]) / abs(a["E"]) for a, c in zip(st, stc))
+        log("batched cascadic solve: %.2f s (coarse levels %.2f s), %d/%d converged, max finest-mesh hvp %d, "
+            "max relative energy difference to the one-mesh solves %.1e" % (
+                tc, stc[0]["t_coarse"], convc, count, max(s["hvp_calls"] for s in stc), dEc))
+        out["solve_cascadic"] = {"tol": 1e-6, "mg_levels": stc[0]["mg_levels"], "batched_s": round(tc, 3),
+                                 "coarse_levels_s": round(stc[0]["t_coarse"], 3), "converged": convc,
+                                 "max_hvp_calls_finest_mesh": max(s["hvp_calls"] for s in stc),
+                                 "total_hvp_calls_finest_mesh": sum(s["hvp_calls"] for s in stc),
+                                 "max_rel_energy_diff_vs_one_mesh": dEc}
         if sequential:
             dE = max(abs(a["E"] - e) / abs(e) for a, e in zip(st, E1))
             log("one-by-one solves: %.2f s; max relative energy difference %.2e" % (ts, dE))

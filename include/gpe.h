@@ -331,11 +331,16 @@ gpe_status gpe_batch_hvp(gpe_batch* b, const void* const* Z, void* const* HZ, in
                          double* kappa);
 
 /* gpe_newton_solve for every problem (X_inout[i] c128, stats: count records
- * or NULL) in lock step.  opts->mg_levels must be 0.  Returns GPE_OK when
+ * or NULL) in lock step.  opts->mg_levels > 0: the cascadic hierarchy of
+ * Algorithm 1 for the whole batch, level by level: each coarser level is a
+ * batch of its own (created and destroyed inside the call), solved in lock
+ * step to mg_coarse_tol, and every problem's solution is prolonged to the
+ * next finer level.  Fewer levels are used where a coarse axis would fall
+ * below 16 points; stats[i].mg_levels says how many.  Returns GPE_OK when
  * every problem converged, GPE_ENOTCONV when some did not (their stats say
  * which), else the first problem's error.  t_total, t_rgbb and t_arnt of a
  * problem are wall-clock times of the whole batch's run up to that
- * problem's end of the phase. */
+ * problem's end of the phase; t_coarse is the coarse levels' time. */
 gpe_status gpe_batch_newton_solve(gpe_batch* b, void* const* X_inout, const gpe_solve_opts* opts,
                                   gpe_solve_stats* stats);
 

@@ -877,40 +877,169 @@ gpe_status gpe_batch_hvp(gpe_batch* b, const void* const* Z, void* const* HZ, in
   return GPE_OK;
 }
 
+}  // extern "C"
+
+namespace gpe {
+namespace {
+
+// One lock-step solve of every problem of b on its own mesh (opts->mg_levels
+// is ignored).  status[i]: problem i's own outcome.
+gpe_status lockstep_solve(gpe_batch* b, void* const* X, const gpe_solve_opts& o, gpe_solve_stats* st,
+                          std::vector<gpe_status>* status) {
+  const size_t m = b->hs.size();
+  gpe_solve_opts oo = o;
+  oo.mg_levels = 0;
+  oo.trace = nullptr;   // one trace buffer cannot serve many problems
+  oo.trace_cap = 0;
+  std::vector<Ctx> cs(m);
+  std::vector<Ctx*> cp(m);
+  for (size_t i = 0; i < m; ++i) {
+    std::memset(&st[i], 0, sizeof(st[i]));
+    cs[i].h = b->hs[i];
+    cp[i] = &cs[i];
+  }
+  for (size_t i = 0; i < m; ++i) cs[i].task = solve_task(cs[i], X[i], &oo, &st[i]);
+  Lockstep ls(b);
+  const gpe_status rs = ls.run(cp);
+  status->resize(m);
+  for (size_t i = 0; i < m; ++i) (*status)[i] = cs[i].status;
+  return rs;
+}
+
+// Coarse levels of the cascadic hierarchy (Algorithm 1, outer loop) for a
+// whole batch: level l halves every axis of level l - 1, with V and the
+// initial states injected; each level is a batch of its own, solved in lock
+// step to the coarse tolerance, and every problem's solution is prolonged to
+// the next finer level.  On return X holds the prolonged states on b's grids.
+gpe_status cascadic_levels(gpe_batch* b, void* const* X, const gpe_solve_opts& o, int L, double* t_coarse) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  const size_t m = b->hs.size();
+  std::vector<gpe_batch*> bs(L + 1, nullptr);
+  std::vector<std::vector<void*>> xs(L + 1, std::vector<void*>(m, nullptr));
+  bs[0] = b;
+  for (size_t i = 0; i < m; ++i) xs[0][i] = X[i];
+  gpe_status rs = GPE_OK;
+  for (int l = 1; l <= L && rs == GPE_OK; ++l) {
+    const gpe_batch* f = bs[l - 1];
+    std::vector<gpe_problem> pc(m);
+    std::vector<std::vector<double>> Vc(m);
+    std::vector<const double*> vp(m);
+    for (size_t i = 0; i < m; ++i) {
+      const gpe_handle* h = f->hs[i];
+      pc[i] = h->prob;
+      int nc[3] = {1, 1, 1};
+      for (int a = 0; a < h->dim; ++a) nc[a] = pc[i].n[a] = h->n[a] / 2;
+      Vc[i].resize((size_t)nc[0] * nc[1] * nc[2]);
+      const int sy = h->dim > 1 ? 2 : 1, sz = h->dim > 2 ? 2 : 1;
+      for (int z = 0; z < nc[2]; ++z)
+        for (int y = 0; y < nc[1]; ++y)
+          for (int x = 0; x < nc[0]; ++x)
+            Vc[i][((size_t)z * nc[1] + y) * nc[0] + x] =
+                h->Vhost[((size_t)(z * sz) * h->n[1] + (size_t)(y * sy)) * h->n[0] + 2 * x];
+      vp[i] = Vc[i].data();
+    }
+    rs = gpe_batch_create(pc.data(), vp.data(), (int)m, b->prec, b->st, &bs[l]);
+    if (rs != GPE_OK) {
+      b->err = std::string("multigrid: coarse batch: ") + gpe_batch_last_error(nullptr);
+      bs[l] = nullptr;
+      break;
+    }
+    for (size_t i = 0; i < m && rs == GPE_OK; ++i) {
+      const gpe_handle* hc = bs[l]->hs[i];
+      rs = alloc_field(b->hs[i], &xs[l][i], hc->nel * 16);
+      if (rs != GPE_OK) {
+        b->err = b->hs[i]->err;
+        break;
+      }
+      int nc[3] = {hc->n[0], hc->n[1], hc->n[2]};
+      const hipError_t e = restrict_inject(xs[l - 1][i], xs[l][i], hc->K, hc->dim, nc, std::pow(2.0, 0.5 * hc->dim),
+                                           b->st);
+      if (e != hipSuccess) {
+        rs = hip_fail(b->hs[i], e, "restrict_inject");
+        b->err = b->hs[i]->err;
+      }
+    }
+  }
+  for (int l = L; l >= 1 && rs == GPE_OK; --l) {
+    gpe_solve_opts oc = o;
+    oc.tol = o.mg_coarse_tol;
+    if (o.time_limit > 0)
+      oc.time_limit = std::fmax(o.time_limit - std::chrono::duration<double>(clock::now() - t0).count(), 1e-3);
+    std::vector<gpe_solve_stats> sc(m);
+    std::vector<gpe_status> stat;
+    rs = lockstep_solve(bs[l], xs[l].data(), oc, sc.data(), &stat);
+    if (rs != GPE_OK) {
+      b->err = "multigrid: coarse solve: " + (bs[l]->err.empty() ? bs[l]->hs[0]->err : bs[l]->err);
+      break;
+    }
+    for (size_t i = 0; i < m && rs == GPE_OK; ++i)
+      if (stat[i] != GPE_OK && stat[i] != GPE_ENOTCONV) {
+        rs = stat[i];
+        b->err = "multigrid: coarse solve of problem " + std::to_string(i) + ": " + bs[l]->hs[i]->err;
+      }
+    for (size_t i = 0; i < m && rs == GPE_OK; ++i) {
+      rs = prolong(bs[l]->hs[i], xs[l][i], bs[l - 1]->hs[i], xs[l - 1][i]);
+      if (rs != GPE_OK) b->err = "multigrid: prolong problem " + std::to_string(i) + ": " + bs[l - 1]->hs[i]->err;
+    }
+  }
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  for (int l = 1; l <= L; ++l) {
+    for (void* p : xs[l])
+      if (p) (void)hipFree(p);
+    if (bs[l]) gpe_batch_destroy(bs[l]);
+  }
+  *t_coarse = std::chrono::duration<double>(clock::now() - t0).count();
+  return rs;
+}
+
+}  // namespace
+}  // namespace gpe
+
+extern "C" {
+
 gpe_status gpe_batch_newton_solve(gpe_batch* b, void* const* X_inout, const gpe_solve_opts* opts,
                                   gpe_solve_stats* stats) {
   if (!b || !X_inout) return batch_fail(b, GPE_EINVAL, "NULL argument");
   gpe_solve_opts o;
   if (opts) o = *opts;
   else gpe_solve_opts_default(&o);
-  if (o.mg_levels > 0) return batch_fail(b, GPE_EINVAL, "a batch solves on one mesh (mg_levels must be 0)");
-  o.trace = nullptr;   // one trace buffer cannot serve many problems
-  o.trace_cap = 0;
+  if (o.mg_levels < 0) return batch_fail(b, GPE_EINVAL, "mg_levels must be >= 0");
   const size_t m = b->hs.size();
-  std::vector<gpe_solve_stats> st(m);
-  std::vector<Ctx> cs(m);
-  std::vector<Ctx*> cp(m);
-  for (size_t i = 0; i < m; ++i) {
+  for (size_t i = 0; i < m; ++i)
     if (!X_inout[i]) return batch_fail(b, GPE_EINVAL, "NULL field");
-    std::memset(&st[i], 0, sizeof(st[i]));
-    cs[i].h = b->hs[i];
-    cp[i] = &cs[i];
+  // the coarsest admissible level: every axis of every problem stays a batch size (a power of two >= 16)
+  int L = o.mg_levels;
+  for (size_t i = 0; i < m; ++i)
+    for (int a = 0; a < b->dim; ++a)
+      while (L > 0 && !batch_size_supported(b->hs[i]->n[a] >> L)) --L;
+  double t_coarse = 0.0;
+  b->err.clear();
+  if (L > 0) {
+    const gpe_status r = cascadic_levels(b, X_inout, o, L, &t_coarse);
+    if (r != GPE_OK) return batch_fail(b, r, b->err.empty() ? "multigrid failed" : b->err);
+    if (o.time_limit > 0) o.time_limit = std::fmax(o.time_limit - t_coarse, 1e-3);
   }
-  for (size_t i = 0; i < m; ++i) cs[i].task = solve_task(cs[i], X_inout[i], &o, &st[i]);
-  Lockstep ls(b);
-  const gpe_status rs = ls.run(cp);
+  std::vector<gpe_solve_stats> st(m);
+  std::vector<gpe_status> stat;
+  const gpe_status rs = lockstep_solve(b, X_inout, o, st.data(), &stat);
+  for (size_t i = 0; i < m; ++i) {   // counters: finest mesh only
+    st[i].mg_levels = L;
+    st[i].t_coarse = t_coarse;
+    st[i].t_total += t_coarse;
+  }
   if (stats)
     for (size_t i = 0; i < m; ++i) stats[i] = st[i];
   if (rs != GPE_OK) return batch_fail(b, rs, b->err.empty() ? b->hs[0]->err : b->err);
   gpe_status agg = GPE_OK;
   for (size_t i = 0; i < m && agg == GPE_OK; ++i)
-    if (cs[i].status != GPE_OK && cs[i].status != GPE_ENOTCONV) {
-      agg = cs[i].status;
+    if (stat[i] != GPE_OK && stat[i] != GPE_ENOTCONV) {
+      agg = stat[i];
       b->err = "problem " + std::to_string(i) + ": " + b->hs[i]->err;
     }
   if (agg == GPE_OK)
     for (size_t i = 0; i < m; ++i)
-      if (cs[i].status == GPE_ENOTCONV) {
+      if (stat[i] == GPE_ENOTCONV) {
         agg = GPE_ENOTCONV;
         b->err = "problem " + std::to_string(i) + ": tolerance not reached";
         break;

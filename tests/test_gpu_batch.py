@@ -126,6 +126,45 @@ def test_batch_solve_mixed_uneven_grids(torch):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_cascadic_solve_matches_single(torch, precision):
+    """The batch through the cascadic hierarchy (one coarser mesh per problem,
+    every coarse level a lock-step batch of its own) against each problem's
+    own cascadic solve: same energies, constraints exact."""
+    from paper_1907_01194_amd.binding import Batch, Problem
+    from gpu_util import dev
+    specs = W.spin1_2d_batch(count=5, seed=8, sizes=(32, 64))
+    X0 = [W.initial_state(sp, 60 + i) for i, sp in enumerate(specs)]
+    print("batch cascadic", precision, [(s.n, s.beta[1], s.M) for s in specs], flush=True)
+    b = Batch(specs, precision)
+    _, stats = b.newton_solve([dev(x) for x in X0], tol=1e-6, mg_levels=1, time_limit=100.0)
+    b.close()
+    tol_e = 1e-10 if precision == "fp64" else 1e-6
+    for i, sp in enumerate(specs):
+        st = stats[i]
+        assert st["converged"] and st["mg_levels"] == 1 and st["t_coarse"] > 0, (i, st)
+        assert st["mass_err"] <= 1e-12 and st["mag_err"] <= 1e-12
+        p = Problem(sp, precision)
+        _, s1 = p.newton_solve(dev(X0[i]), tol=1e-6, mg_levels=1, time_limit=100.0)
+        p.close()
+        assert s1["converged"] and s1["mg_levels"] == 1
+        assert abs(st["E"] - s1["E"]) <= tol_e * abs(s1["E"]), (i, st["E"], s1["E"])
+
+
+def test_batch_cascadic_levels_limited_by_smallest_grid(torch):
+    """A batch with a 32^2 problem can take one coarser level (16^2), not two."""
+    from paper_1907_01194_amd.binding import Batch
+    from gpu_util import dev
+    specs = W.spin1_2d_batch(count=3, seed=9, sizes=(32, 64))
+    specs = [sp for sp in specs] + [W.spin1_2d_batch(count=1, seed=3, sizes=(32,))[0]]
+    X0 = [W.initial_state(sp, 70 + i) for i, sp in enumerate(specs)]
+    print("batch cascadic levels", [s.n for s in specs], flush=True)
+    b = Batch(specs, "fp64")
+    _, stats = b.newton_solve([dev(x) for x in X0], check=False, tol=1e-6, mg_levels=3, time_limit=100.0)
+    b.close()
+    assert all(st["mg_levels"] == 1 for st in stats)
+
+
 def test_batch_solve_small_cg_cap(torch):
     """Every truncated CG of the run stops at a cap of 4 iterations or earlier
     (the cap stop updates z but not p, in the closing step of the iteration
