@@ -123,13 +123,16 @@ struct LineCtx {
 };
 
 // Padded LDS layout of a line held contiguously: element j sits at
-// j + j/8.  The Stockham passes access a line at strides R (the first
-// pass's writes: 8 for radix 8) and 2rk (twiddles); one pad per 8 elements
-// spreads every such group of lanes over distinct banks, for 8- and
-// 16-byte elements alike.
-__host__ __device__ constexpr int pad8(int j) { return j + (j >> 3); }
+// j + (j >> pad_shift<T>()), one pad per pad_run<T>() elements: 16 for c64
+// lines, 8 for c128 lines (the run with the fewest bank conflicts for each
+// element size).  The Stockham passes access a line at strides R (the first
+// pass's writes: 8 for radix 8) and 2rk (twiddles); the pads spread every such
+// group of lanes over distinct banks.
+template <typename T> __host__ __device__ constexpr int pad_shift() { return sizeof(T) == 4 ? 4 : 3; }
+template <typename T> __host__ __device__ constexpr int pad_run() { return 1 << pad_shift<T>(); }
+template <typename T> __host__ __device__ constexpr int lpad(int j) { return j + (j >> pad_shift<T>()); }
 // LDS elements a padded line (or twiddle table) of length N occupies
-__host__ __device__ constexpr int padded_len(int N) { return N + (N >> 3) + 1; }
+template <typename T> __host__ __device__ constexpr int padded_len(int N) { return N + (N >> pad_shift<T>()) + 1; }
 
 // Epilogue of the last inverse pass: out = acc + val - pc * X (pc = 0: no projection).
 template <typename T> struct Epi {
@@ -138,12 +141,12 @@ template <typename T> struct Epi {
   T pc;
 };
 
-// PAD: the line is contiguous in LDS in the padded layout (pad8), and so is
+// PAD: the line is contiguous in LDS in the padded layout (lpad), and so is
 // the twiddle table; otherwise element j of the line is at lbase + j lstride
 // and twiddle m at m.  raw (first pass only, may be null): the line as read
 // from global memory is also stored there, in the line's own LDS layout.
-template <bool PAD> __device__ __forceinline__ int lidx(const LineCtx& lc, int j) {
-  return PAD ? lc.lbase + pad8(j) : lc.lbase + j * lc.lstride;
+template <typename T, bool PAD> __device__ __forceinline__ int lidx(const LineCtx& lc, int j) {
+  return PAD ? lc.lbase + lpad<T>(j) : lc.lbase + j * lc.lstride;
 }
 
 template <typename T, int N, int s, bool FWD, int SRC, int DST, bool PAD>
@@ -160,17 +163,17 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
   constexpr int NB = (B + TPL - 1) / TPL;
   constexpr bool LAST_FWD = FWD && (s == P.S - 1);
   T2 v[NB][R];
-  // padded reads at j = b + r B: with B a multiple of 8, pad8(j) = pad8(b) + pad8(r B)
-  constexpr bool kReadSplit = PAD && B % 8 == 0;
+  // padded reads at j = b + r B: with B a multiple of the pad run, lpad(j) = lpad(b) + lpad(r B)
+  constexpr bool kReadSplit = PAD && B % pad_run<T>() == 0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = lc.tl + i * TPL;
     if (lc.valid && (B % TPL == 0 || b < B)) {
-      const int pb = lc.lbase + pad8(b);
+      const int pb = lc.lbase + lpad<T>(b);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int j = b + r * B;
-        const int li = kReadSplit ? pb + pad8(r * B) : lidx<PAD>(lc, j);
+        const int li = kReadSplit ? pb + lpad<T>(r * B) : lidx<T, PAD>(lc, j);
         v[i][r] = (SRC == SRC_GLOBAL) ? gin[lc.goff + (size_t)j * lc.gstride] : lds[li];
         if (SRC == SRC_GLOBAL && raw) raw[li] = v[i][r];
       }
@@ -186,7 +189,7 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           const int m = (r * k * (N / (Ns * R))) % N;
-          T2 w = tw[PAD ? pad8(m) : m];
+          T2 w = tw[PAD ? lpad<T>(m) : m];
           if (!FWD) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -194,13 +197,14 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
       Dft<R, FWD, T2>::run(v[i]);
       const int base = (b / Ns) * Ns * R + k;
       // padded writes at base + r Ns: split as for the reads when Ns is a
-      // multiple of 8, or when Ns = 1 and base is (R = 8)
-      constexpr bool kWriteSplit = PAD && (Ns % 8 == 0 || (Ns == 1 && R == 8));
-      const int pbase = lc.lbase + pad8(base);
+      // multiple of the pad run, or when Ns = 1 and R divides the pad run
+      // (base = R b, and base + r never carries into the pad count)
+      constexpr bool kWriteSplit = PAD && (Ns % pad_run<T>() == 0 || (Ns == 1 && pad_run<T>() % R == 0));
+      const int pbase = lc.lbase + lpad<T>(base);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = base + r * Ns;
-        const int lw = kWriteSplit ? pbase + (Ns == 1 ? r : pad8(r * Ns)) : lidx<PAD>(lc, idx);
+        const int lw = kWriteSplit ? pbase + (Ns == 1 ? r : lpad<T>(r * Ns)) : lidx<T, PAD>(lc, idx);
         T2 val = v[i][r];
         if (LAST_FWD) {
           const int p = idx < N / 2 ? idx : idx - N;
@@ -390,12 +394,12 @@ template <int N, int K, int VAR = 1> struct XGeo {
   // LDS: the padded twiddle table, then LINES padded lines, then (FP64 only)
   // LINES more holding the rows of Z as read (the pointwise terms take Z
   // from there instead of reading global memory a second time)
-  static constexpr int LSTR = padded_len(N);
+  template <typename T> static constexpr int lstr() { return padded_len<T>(N); }
   template <typename T> static constexpr bool stash() {
-    return sizeof(T) == 8 && 2 * sizeof(T) * ((size_t)LSTR + 2 * (size_t)LINES * LSTR) <= 150 * 1024;
+    return sizeof(T) == 8 && 2 * sizeof(T) * ((size_t)lstr<T>() + 2 * (size_t)LINES * lstr<T>()) <= 150 * 1024;
   }
   template <typename T> static constexpr size_t lds_elems() {
-    return (size_t)LSTR + (size_t)LINES * LSTR * (stash<T>() ? 2 : 1);
+    return (size_t)lstr<T>() + (size_t)LINES * lstr<T>() * (stash<T>() ? 2 : 1);
   }
 };
 
@@ -412,14 +416,14 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
   using G = XGeo<N, K, VAR>;
   constexpr int RPB = G::RPB;
   constexpr int LINES = G::LINES;
-  constexpr int LSTR = G::LSTR;
+  constexpr int LSTR = G::template lstr<T>();
   constexpr bool kStash = G::template stash<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* tw = reinterpret_cast<T2*>(smem_raw);
   T2* lds = tw + LSTR;
   T2* zraw = kStash ? lds + LINES * LSTR : nullptr;
   const int t = threadIdx.x;
-  for (int m = t; m < N; m += blockDim.x) tw[pad8(m)] = twg[m];
+  for (int m = t; m < N; m += blockDim.x) tw[lpad<T>(m)] = twg[m];
   const long row0 = blk * RPB;
 
   // ---- prefetch the global pointwise operands of this thread's first point
@@ -445,7 +449,7 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
   auto load_stashed = [&]() {
     if constexpr (kStash) {
 #pragma unroll
-      for (int i = 0; i < K; ++i) z[i] = zraw[(i * RPB + pt / N) * LSTR + pad8(pt % N)];
+      for (int i = 0; i < K; ++i) z[i] = zraw[(i * RPB + pt / N) * LSTR + lpad<T>(pt % N)];
     }
   };
   if (have) load_global();
@@ -486,7 +490,7 @@ __device__ __forceinline__ void xpass_body(const c_t<T>* __restrict__ X, const c
       s_zz += cabs2(z[i]);
     }
     hvp_point<T, F>(x, z, vj, p, zcoef, [&](int i, T2 qi) {
-      const T2 lz = lds[(i * RPB + rr) * LSTR + pad8(xx)];
+      const T2 lz = lds[(i * RPB + rr) * LSTR + lpad<T>(xx)];
       W[i * npts + j] = cadd(lz, qi);
       const T xq = cdotr(x[i], qi);
       s_xw += xq;
