@@ -43,40 +43,40 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes), by precision and
 # schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": "ea25f777a76b97bf",
+    "src_hash": "808bb543ac542105",
     "traffic": {
         "fp64": {
             "0": {
-                "hvp_xpass": 960305941,
-                "lap_axis_y": 705198546,
-                "lap_axis_z": 939952110
+                "hvp_xpass": 960317077,
+                "lap_axis_y": 705329766,
+                "lap_axis_z": 939948142
             },
             "1": {
-                "hvp_xpass": 958477089,
-                "lap_axis_y": 705198546,
-                "lap_axis_z": 939952110
+                "hvp_xpass": 958480640,
+                "lap_axis_y": 705329766,
+                "lap_axis_z": 939948142
             },
             "2": {
-                "hvp_xpass": 957670519,
-                "lap_axis_y": 705198546,
-                "lap_axis_z": 939952110
+                "hvp_xpass": 957679990,
+                "lap_axis_y": 705329766,
+                "lap_axis_z": 939948142
             }
         },
         "mixed": {
             "0": {
-                "hvp_xpass": 479323384,
-                "lap_axis_y": 352821751,
-                "lap_axis_z": 469991248
+                "hvp_xpass": 479322505,
+                "lap_axis_y": 352690691,
+                "lap_axis_z": 469991056
             },
             "1": {
-                "hvp_xpass": 478847786,
-                "lap_axis_y": 352821751,
-                "lap_axis_z": 469991248
+                "hvp_xpass": 478880487,
+                "lap_axis_y": 352690691,
+                "lap_axis_z": 469991056
             },
             "2": {
-                "hvp_xpass": 478603259,
-                "lap_axis_y": 352821751,
-                "lap_axis_z": 469991248
+                "hvp_xpass": 478603531,
+                "lap_axis_y": 352690691,
+                "lap_axis_z": 469991056
             }
         }
     },
@@ -87,9 +87,9 @@ MEASURED = {
             "2": 64040960
         },
         "mixed": {
-            "0": 66453504,
-            "1": 66240512,
-            "2": 63242240
+            "0": 67600384,
+            "1": 67371008,
+            "2": 64229376
         }
     }
 }
