@@ -133,6 +133,15 @@ template <typename T> __host__ __device__ constexpr int pad_run() { return 1 << 
 template <typename T> __host__ __device__ constexpr int lpad(int j) { return j + (j >> pad_shift<T>()); }
 // LDS elements a padded line (or twiddle table) of length N occupies
 template <typename T> __host__ __device__ constexpr int padded_len(int N) { return N + (N >> pad_shift<T>()) + 1; }
+// Index shortcuts of a padded pass with B = N / R butterflies and stride Ns:
+// reads at b + r B may be taken as lpad(b) + lpad(r B) when B is a multiple of
+// the pad run; writes at base + r Ns (base = (b / Ns) Ns R + b % Ns) as
+// lpad(base) + lpad(r Ns) when Ns is, or as lpad(base) + r when Ns = 1 and R
+// divides the pad run (base + r then never carries into the pad count).
+template <typename T> __host__ __device__ constexpr bool read_split(int B) { return B % pad_run<T>() == 0; }
+template <typename T> __host__ __device__ constexpr bool write_split(int Ns, int R) {
+  return Ns % pad_run<T>() == 0 || (Ns == 1 && pad_run<T>() % R == 0);
+}
 
 // Epilogue of the last inverse pass: out = acc + val - pc * X (pc = 0: no projection).
 template <typename T> struct Epi {
@@ -163,8 +172,7 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
   constexpr int NB = (B + TPL - 1) / TPL;
   constexpr bool LAST_FWD = FWD && (s == P.S - 1);
   T2 v[NB][R];
-  // padded reads at j = b + r B: with B a multiple of the pad run, lpad(j) = lpad(b) + lpad(r B)
-  constexpr bool kReadSplit = PAD && B % pad_run<T>() == 0;
+  constexpr bool kReadSplit = PAD && read_split<T>(B);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = lc.tl + i * TPL;
@@ -196,10 +204,7 @@ __device__ __forceinline__ void stage(const c_t<T>* __restrict__ gin, c_t<T>* ld
       }
       Dft<R, FWD, T2>::run(v[i]);
       const int base = (b / Ns) * Ns * R + k;
-      // padded writes at base + r Ns: split as for the reads when Ns is a
-      // multiple of the pad run, or when Ns = 1 and R divides the pad run
-      // (base = R b, and base + r never carries into the pad count)
-      constexpr bool kWriteSplit = PAD && (Ns % pad_run<T>() == 0 || (Ns == 1 && pad_run<T>() % R == 0));
+      constexpr bool kWriteSplit = PAD && write_split<T>(Ns, R);
       const int pbase = lc.lbase + lpad<T>(base);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
