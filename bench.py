@@ -43,40 +43,40 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions (SQ_INSTS_VALU, per wavefront; x64 lanes), by precision and
 # schedule variant; valid only while the kernel sources hash to `src_hash`.
 MEASURED = {
-    "src_hash": "808bb543ac542105",
+    "src_hash": "b9479596af174dd3",
     "traffic": {
         "fp64": {
             "0": {
-                "hvp_xpass": 960317077,
-                "lap_axis_y": 705329766,
-                "lap_axis_z": 939948142
+                "hvp_xpass": 960321477,
+                "lap_axis_y": 705329830,
+                "lap_axis_z": 939946766
             },
             "1": {
-                "hvp_xpass": 958480640,
-                "lap_axis_y": 705329766,
-                "lap_axis_z": 939948142
+                "hvp_xpass": 958474865,
+                "lap_axis_y": 705329830,
+                "lap_axis_z": 939946766
             },
             "2": {
-                "hvp_xpass": 957679990,
-                "lap_axis_y": 705329766,
-                "lap_axis_z": 939948142
+                "hvp_xpass": 957689317,
+                "lap_axis_y": 705329830,
+                "lap_axis_z": 939946766
             }
         },
         "mixed": {
             "0": {
-                "hvp_xpass": 479322505,
-                "lap_axis_y": 352690691,
-                "lap_axis_z": 469991056
+                "hvp_xpass": 479323960,
+                "lap_axis_y": 352821879,
+                "lap_axis_z": 469991312
             },
             "1": {
-                "hvp_xpass": 478880487,
-                "lap_axis_y": 352690691,
-                "lap_axis_z": 469991056
+                "hvp_xpass": 478860473,
+                "lap_axis_y": 352821879,
+                "lap_axis_z": 469991312
             },
             "2": {
-                "hvp_xpass": 478603531,
-                "lap_axis_y": 352690691,
-                "lap_axis_z": 469991056
+                "hvp_xpass": 478603403,
+                "lap_axis_y": 352821879,
+                "lap_axis_z": 469991312
             }
         }
     },
