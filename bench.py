@@ -20,7 +20,7 @@ the batched form (64 spin-1 2D problems of uneven grids in one gpe_batch: one
 batched HVP pass against the same HVPs one by one, and the lock-step Newton
 solve against one-by-one solves) and the CPU oracle's timings.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-solve] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 100] [--no-solve] [--no-cpu]
                     [--no-batch] [--no-batch-solve] [--no-batch-sequential] [--batch-only]
 """
 
@@ -119,7 +119,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
     ap.add_argument("--no-solve", action="store_true", help="skip time-to-ground-state")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
@@ -216,6 +216,15 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log, variant=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
+    # five more repetitions of the same (reported beside the timed region: their median)
+    reps = []
+    for _ in range(5):
+        e0.record(stream)
+        for _ in range(steps):
+            gp.hvp(Z, True, 1e-2, out=HZ)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / steps)
     # (2) with the read-back of kappa = <Z, HZ> after every HVP (one synchronisation each)
     e0.record(stream)
     kappa = 0.0
@@ -239,10 +248,12 @@ def time_hvps(spec, prec, w, noise, steps, warmup, log, variant=None):
                                                                      1e3 * ms_dot, kappa))
     for k, (c, t) in sorted(kt.items(), key=lambda x: -x[1][1]):
         log("   %-12s %6d launches  %9.1f us avg" % (k, c, 1e3 * t / c))
+    log("%s: five more repetitions: %s us per HVP (median %.1f)" % (
+        prec, ", ".join("%.1f" % (1e3 * r) for r in reps), 1e3 * float(np.median(reps))))
     gp.close()
     del gp
     torch.cuda.empty_cache()
-    return ms, ms_dot, kt, sched
+    return ms, ms_dot, kt, sched, reps
 
 
 def roofline(spec, prec, ms, kt, variant, steps):
@@ -668,8 +679,10 @@ def main():
     noise = W.random_direction(spec, 103)
     res = {}
     for prec in precs:
-        ms, ms_dot, kt, sched = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log, args.variant)
+        ms, ms_dot, kt, sched, reps = time_hvps(spec, prec, w, noise, args.steps, args.warmup, log, args.variant)
         res[prec] = {"ms_per_hvp": ms, "hvp_per_s": 1e3 / ms, "ms_per_hvp_with_kappa_readback": ms_dot,
+                     "ms_per_hvp_repetitions": [round(r, 4) for r in reps],
+                     "ms_per_hvp_median_of_5": round(float(np.median(reps)), 4),
                      "roofline": roofline(spec, prec, ms, kt, sched[0], args.steps),
                      "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()},
                      "kernel_launches_per_hvp": {k: round(c / args.steps, 2) for k, (c, t) in kt.items()},
@@ -733,6 +746,8 @@ def main():
         "cpu_baseline": cpu,
         "precisions": {p: {"hvp_per_s": round(r["hvp_per_s"], 2), "ms_per_hvp": round(r["ms_per_hvp"], 4),
                            "ms_per_hvp_with_kappa_readback": round(r["ms_per_hvp_with_kappa_readback"], 4),
+                           "ms_per_hvp_median_of_5": r["ms_per_hvp_median_of_5"],
+                           "ms_per_hvp_repetitions": r["ms_per_hvp_repetitions"],
                            "roofline": r["roofline"], "kernels_us": r["kernels_us"],
                            "kernel_launches_per_hvp": r["kernel_launches_per_hvp"],
                            "xpass_schedule": r["xpass_schedule"]} for p, r in res.items()},
